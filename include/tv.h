@@ -1,0 +1,127 @@
+/*
+ * tv.h -- C ABI of the gfx950 tetrahedral-mesh voxelizer.
+ *
+ * The operation (the paper's voxelization, Section 3 "Voxelization", with the
+ * point-in-tet test of Theorem 1, Section 4): for every tetrahedron, every
+ * voxel center inside it sets that voxel in a solid binary occupancy grid
+ * (the paper voxelizes into a 256^3 binary grid, Table 1).  The library
+ * computes this exactly:
+ *
+ *   - vertices are first placed on a fixed-point lattice of 2^16 units per
+ *     bbox extent and per axis (see "Snap" below); all later arithmetic is
+ *     exact integer arithmetic on that lattice;
+ *   - the sample point of voxel (i,j,k) is its center; with S_a = 2^15 / N_a
+ *     the center is ((2i+1)S_x, (2j+1)S_y, (2k+1)S_z) in lattice units;
+ *   - a center is inside a tet when all four barycentric coordinates are
+ *     positive -- the same decision as Theorem 1's four determinant signs --
+ *     and, in TV_TIE_HALF_OPEN mode (the default), a center lying exactly on
+ *     a face takes the side it is on after a push by eps*ez + eps^2*ey +
+ *     eps^3*ex (eps -> 0+).  In a conforming mesh every center of the union's
+ *     interior is then covered exactly once.  TV_TIE_STRICT applies Theorem 1
+ *     literally (points on a face are outside), which leaves shared faces
+ *     uncovered;
+ *   - degenerate (zero-volume) tets add nothing, either vertex orientation is
+ *     accepted (Lemma 1.1), overlapping tets give the union.
+ *
+ * Snap (fp32 input only): per axis a,
+ *     q = rint(((double)v - (double)lo[a]) * 65536.0 / ((double)hi[a] - (double)lo[a]))
+ * evaluated left to right in IEEE double, round-to-nearest-even, no fused
+ * multiply-add.  A NaN or a q outside [TV_Q_MIN, TV_Q_MAX] is a data error.
+ *
+ * Grid layout: W = ceil(nz/32) uint32 words per (i,j) column; voxel (i,j,k)
+ * is bit (k & 31) of word (i*ny + j)*W + (k >> 5).  The whole grid
+ * (nx*ny*W words, padding bits included) is overwritten; padding bits are 0.
+ *
+ * Memory and streams: every data pointer is a DEVICE pointer owned by the
+ * caller; the library allocates nothing.  Scratch space is the caller's
+ * workspace `ws` of at least the size the matching *_workspace_bytes call
+ * returns, aligned to 256 bytes.  Calls are asynchronous on `stream` (a
+ * hipStream_t; NULL is the default stream) and return after enqueueing.
+ * Calls on different streams with different workspaces may run concurrently;
+ * two calls sharing a workspace must be ordered on one stream.
+ *
+ * Errors: argument errors that the host can see (null pointers, sizes, dims,
+ * bbox, workspace size) return synchronously and enqueue nothing.  Data errors
+ * found on the device (a tet index outside [0,nv), a NaN or out-of-range
+ * coordinate) are recorded in the workspace; the offending tets are skipped
+ * and the grid is still written.  Read them with tv_fetch_status after the
+ * work has been enqueued (it synchronizes `stream`).
+ */
+#ifndef TV_H
+#define TV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t tv_status;
+#define TV_OK 0
+#define TV_ERR_INVALID_ARG (-1)      /* null pointer, negative size, bad bbox/flags */
+#define TV_ERR_UNSUPPORTED_DIMS (-2) /* a dim that is not a power of two in [1, 32768] */
+#define TV_ERR_INDEX (-3)            /* (device) a tet index outside [0, nv) */
+#define TV_ERR_RANGE (-4)            /* (device) NaN or coordinate off the lattice range */
+#define TV_ERR_WORKSPACE (-5)        /* workspace null, misaligned or too small */
+#define TV_ERR_HIP (-7)              /* a HIP runtime call failed */
+
+#define TV_Q_MIN (-16384)        /* lattice range: [-2^14, 2^16 + 2^14] per axis */
+#define TV_Q_MAX (65536 + 16384)
+
+/* flags */
+#define TV_TIE_HALF_OPEN 0u /* default tie rule (see above) */
+#define TV_TIE_STRICT 1u    /* Theorem 1 literally: a center on a face is outside */
+
+typedef struct {
+    int32_t nx, ny, nz; /* each a power of two in [1, 32768] */
+} tv_dims;
+
+typedef struct {
+    float lo[3], hi[3]; /* world box mapped onto lattice [0, 2^16]; hi > lo per axis */
+} tv_bbox;
+
+/* Number of uint32 words of a grid: nx * ny * ceil(nz / 32).  0 for bad dims. */
+size_t tv_grid_words(tv_dims dims);
+
+/* Workspace bytes needed by tv_voxelize / tv_voxelize_q for these sizes. */
+size_t tv_workspace_bytes(int64_t nv, int64_t nt, tv_dims dims, uint32_t flags);
+
+/*
+ * Voxelize one mesh given fp32 world coordinates.
+ *   verts  [nv][3] float32, device, row-major (x, y, z)
+ *   tets   [nt][4] int32, device, vertex indices
+ *   dims   grid resolution; bbox: world box covered by the grid
+ *   grid   [tv_grid_words(dims)] uint32, device, written entirely
+ *   ws     workspace (device, 256-byte aligned, >= tv_workspace_bytes)
+ * nt == 0 is valid and yields an all-zero grid.
+ */
+tv_status tv_voxelize(const float *verts, int64_t nv, const int32_t *tets, int64_t nt,
+                      tv_dims dims, tv_bbox bbox, uint32_t *grid, void *ws, size_t ws_bytes,
+                      void *stream, uint32_t flags);
+
+/* As tv_voxelize, with vertices already on the lattice: qverts [nv][3] int32
+ * (device), each coordinate in [TV_Q_MIN, TV_Q_MAX]. */
+tv_status tv_voxelize_q(const int32_t *qverts, int64_t nv, const int32_t *tets, int64_t nt,
+                        tv_dims dims, uint32_t *grid, void *ws, size_t ws_bytes, void *stream,
+                        uint32_t flags);
+
+/*
+ * Data-error status of mesh `mesh_index` recorded in workspace `ws` by the
+ * last call that used it (index 0 for the single-mesh calls).  Synchronizes
+ * `stream`, then returns TV_OK, TV_ERR_INDEX or TV_ERR_RANGE (TV_ERR_INDEX
+ * wins when both occurred), or TV_ERR_INVALID_ARG / TV_ERR_HIP.
+ */
+tv_status tv_fetch_status(const void *ws, int32_t mesh_index, void *stream);
+
+/* Human-readable name of a status code (static storage). */
+const char *tv_status_string(tv_status s);
+
+/* Message of the last error returned on the calling thread (thread-local). */
+const char *tv_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TV_H */

@@ -1,0 +1,193 @@
+"""gfx950 tetrahedral-mesh voxelizer: thin Python binding over the C ABI.
+
+Every function here only marshals arguments (torch tensors -> device
+pointers, the current HIP stream) and calls ``libtetvox.so``; all work runs in
+the library's HIP kernels.  Importing works without a GPU; calling a compute
+function requires the built library and a GPU, and raises otherwise -- there
+is no CPU fallback.
+
+Grids are returned as torch.int32 tensors holding the uint32 words of the
+layout in include/tv.h: voxel (i,j,k) is bit k%32 of word
+(i*ny + j)*ceil(nz/32) + k//32.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "_lib", "libtetvox.so")
+
+TV_OK = 0
+TV_ERR_INVALID_ARG = -1
+TV_ERR_UNSUPPORTED_DIMS = -2
+TV_ERR_INDEX = -3
+TV_ERR_RANGE = -4
+TV_ERR_WORKSPACE = -5
+TV_ERR_HIP = -7
+
+TIE_HALF_OPEN = 0
+TIE_STRICT = 1
+
+EXPORTED = ("tv_grid_words", "tv_workspace_bytes", "tv_voxelize", "tv_voxelize_q",
+            "tv_fetch_status", "tv_status_string", "tv_last_error")
+
+
+class Dims(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32)]
+
+
+class BBox(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_float * 3), ("hi", ctypes.c_float * 3)]
+
+
+class TVError(RuntimeError):
+    def __init__(self, code, msg=""):
+        super().__init__(f"{status_name(code)}: {msg}" if msg else status_name(code))
+        self.code = code
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return LIB_PATH
+
+
+def load_library():
+    """Load libtetvox.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2106_01326_amd.build` (no CPU fallback exists)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    i64 = ctypes.c_int64
+    u32 = ctypes.c_uint32
+    st = ctypes.c_int32
+    lib.tv_grid_words.argtypes = [Dims]
+    lib.tv_grid_words.restype = ctypes.c_size_t
+    lib.tv_workspace_bytes.argtypes = [i64, i64, Dims, u32]
+    lib.tv_workspace_bytes.restype = ctypes.c_size_t
+    lib.tv_voxelize.argtypes = [P, i64, P, i64, Dims, BBox, P, P, ctypes.c_size_t, P, u32]
+    lib.tv_voxelize.restype = st
+    lib.tv_voxelize_q.argtypes = [P, i64, P, i64, Dims, P, P, ctypes.c_size_t, P, u32]
+    lib.tv_voxelize_q.restype = st
+    lib.tv_fetch_status.argtypes = [P, ctypes.c_int32, P]
+    lib.tv_fetch_status.restype = st
+    lib.tv_status_string.argtypes = [st]
+    lib.tv_status_string.restype = ctypes.c_char_p
+    lib.tv_last_error.argtypes = []
+    lib.tv_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def status_name(code: int) -> str:
+    try:
+        return load_library().tv_status_string(code).decode()
+    except RuntimeError:
+        return f"status {code}"
+
+
+def _check(code: int):
+    if code != TV_OK:
+        raise TVError(code, load_library().tv_last_error().decode())
+
+
+def _dims(dims) -> Dims:
+    nx, ny, nz = (int(d) for d in dims)
+    return Dims(nx, ny, nz)
+
+
+def grid_words(dims) -> int:
+    return int(load_library().tv_grid_words(_dims(dims)))
+
+
+def workspace_bytes(nv: int, nt: int, dims, flags: int = 0) -> int:
+    return int(load_library().tv_workspace_bytes(int(nv), int(nt), _dims(dims), int(flags)))
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def _stream_handle(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_ptr(t, dtype, shape_tail, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if shape_tail is not None and (t.dim() != 2 or t.shape[1] != shape_tail):
+        raise ValueError(f"{name} must have shape [n, {shape_tail}]")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr()), int(t.shape[0])
+
+
+def alloc_workspace(nbytes: int, device=None):
+    torch = _torch()
+    # torch's caching allocator returns 512-byte aligned blocks
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8,
+                       device=device if device is not None else "cuda")
+
+
+def alloc_grid(dims, device=None):
+    torch = _torch()
+    return torch.empty(grid_words(dims), dtype=torch.int32,
+                       device=device if device is not None else "cuda")
+
+
+def voxelize(verts, tets, dims, bbox=None, *, qverts=False, strict=False, grid=None,
+             workspace=None, stream=None):
+    """Voxelize one mesh on the GPU (asynchronous on ``stream``).
+
+    verts: [nv,3] float32 world coordinates (``qverts=False``, needs ``bbox``
+    = (lo[3], hi[3])) or [nv,3] int32 lattice coordinates (``qverts=True``).
+    tets: [nt,4] int32.  Returns (grid, workspace); call ``fetch_status`` on
+    the workspace to read device-side data errors.
+    """
+    lib = load_library()
+    torch = _torch()
+    d = _dims(dims)
+    flags = TIE_STRICT if strict else TIE_HALF_OPEN
+    vptr, nv = _dev_ptr(verts, torch.int32 if qverts else torch.float32, 3, "verts")
+    tptr, nt = _dev_ptr(tets, torch.int32, 4, "tets")
+    if grid is None:
+        grid = alloc_grid(dims, verts.device)
+    gptr, _ = _dev_ptr(grid, torch.int32, None, "grid")
+    if grid.numel() < grid_words(dims):
+        raise ValueError("grid tensor too small")
+    need = workspace_bytes(nv, nt, dims, flags)
+    if workspace is None:
+        workspace = alloc_workspace(need, verts.device)
+    wptr, _ = _dev_ptr(workspace, torch.uint8, None, "workspace")
+    s = _stream_handle(stream)
+    if qverts:
+        rc = lib.tv_voxelize_q(vptr, nv, tptr, nt, d, gptr, wptr, workspace.numel(), s, flags)
+    else:
+        if bbox is None:
+            raise ValueError("fp32 vertices need a bbox")
+        lo, hi = bbox
+        b = BBox((ctypes.c_float * 3)(*[float(x) for x in lo]), (ctypes.c_float * 3)(*[float(x) for x in hi]))
+        rc = lib.tv_voxelize(vptr, nv, tptr, nt, d, b, gptr, wptr, workspace.numel(), s, flags)
+    _check(rc)
+    return grid, workspace
+
+
+def fetch_status(workspace, mesh_index: int = 0, stream=None) -> int:
+    """Device-side data-error status of a finished call (synchronizes)."""
+    lib = load_library()
+    torch = _torch()
+    wptr, _ = _dev_ptr(workspace, torch.uint8, None, "workspace")
+    return int(lib.tv_fetch_status(wptr, int(mesh_index), _stream_handle(stream)))
