@@ -1,0 +1,229 @@
+#!/usr/bin/env python3
+"""Benchmark of the voxelization hot path on one MI355X.
+
+A step is one complete voxelization of one mesh (grid clear, vertex snap,
+per-tet setup and column-span voxelization) with the inputs already resident
+in HBM.  Prints ONE JSON line:
+
+  metric/value/unit   tets voxelized per second (whole job), plus meshes/s
+  roofline            dominant kernel (voxelize) vs the VALU peak
+  cpu_baseline        the CPU oracle timed on a bounded sample of the same
+                      workload on the host's cores (rank 0, N=1 only)
+
+Workloads (seeded synthetic Kuhn meshes, see paper_2106_01326_amd/synth.py):
+  large   128^3 cubes x 6 tets, jitter 0.45, 6 ellipsoids, 1024^3 grid, fp32 (default)
+  medium  64^3 cubes x 6 tets, jitter 0.3, 3 ellipsoids, 256^3 grid, int32 lattice verts
+  small   8^3 cubes x 6 tets, jitter 0.2, sphere, 32^3 grid, fp32
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+LAT = 1 << 16
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12  # 256 CUs x 64 lanes/clk x 2.4 GHz = 39.3 T lane-ops/s
+# Algorithmic VALU lane-operations of the exact column-span formulation:
+SETUP_OPS_PER_TET = 170  # box (min/max/shift/clamp) + 4 faces (edges, cross, orient, tie, base, scales, 1/sz)
+OPS_PER_COLUMN = 24      # 4 faces x (evaluate, quotient estimate, round, exact check, merge) + run write
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def make_workload(name):
+    from paper_2106_01326_amd import synth
+
+    if name == "large":
+        return synth.workload_large()
+    if name == "medium":
+        return synth.workload_medium()
+    if name == "small":
+        return synth.workload_small()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def workload_config(name, m):
+    return {"workload": {"large": "large single mesh (config 2)", "medium": "medium single mesh (config 1)",
+                         "small": "small single mesh (config 0)"}[name],
+            "cubes_per_axis": m.meta["n"], "jitter": m.meta["delta"], "keep": m.meta["keep"],
+            "ellipsoids": m.meta["k"], "grid": list(m.dims), "vert_format": m.fmt,
+            "tets": m.nt, "verts": m.nv, "tets_before_keep": m.meta["tets_before_keep"], "seed_index": True}
+
+
+def candidate_work(q, tets, dims):
+    """(#tets with a non-empty candidate box, #candidate columns, #candidate
+    centers) from the lattice vertices -- counts only, for the roofline."""
+    p = q[tets]  # [nt,4,3]
+    mn = p.min(axis=1).astype(np.int64)
+    mx = p.max(axis=1).astype(np.int64)
+    half = np.array([(LAT // 2) // d for d in dims], dtype=np.int64)
+    lo = np.maximum(0, -((half - mn) // (2 * half)))
+    hi = np.minimum(np.array(dims) - 1, (mx - half) // (2 * half))
+    ext = np.maximum(hi - lo + 1, 0)
+    nonempty = np.all(ext > 0, axis=1)
+    cols = (ext[:, 0] * ext[:, 1])[nonempty]
+    cand = (ext[:, 0] * ext[:, 1] * ext[:, 2])[nonempty]
+    return int(nonempty.sum()), int(cols.sum()), int(cand.sum())
+
+
+def kernel_source_sha():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2106_01326_amd", "csrc")
+    for fn in sorted(os.listdir(csrc)):
+        if fn.endswith((".hip", ".h")):
+            h.update(open(os.path.join(csrc, fn), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(workload):
+    """HBM bytes per voxelize launch from the committed counter summary, or
+    None when absent or taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"traffic_voxelize_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(m, gpu_words_fn, target_s=12.0):
+    """The oracle, as it stands, on a bounded sample (the first tets of the
+    mesh), on all host cores; the GPU path runs the same sample and the two
+    grids are compared bit for bit."""
+    import oracle
+
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    cores = max(1, min(cores, 16))
+    q = oracle.snap(m.verts, *m.bbox) if m.verts is not None else m.qverts
+    probe = min(m.nt, 20000)
+    t0 = time.perf_counter()
+    oracle.voxelize_q(q, m.tets[:probe], m.dims, threads=cores)
+    rate = probe / max(time.perf_counter() - t0, 1e-6)
+    n = int(min(m.nt, max(probe, rate * target_s)))
+    sample = m.tets[:n]
+    t0 = time.perf_counter()
+    if m.verts is not None:
+        want = oracle.voxelize_q(oracle.snap(m.verts, *m.bbox), sample, m.dims, threads=cores)
+    else:
+        want = oracle.voxelize_q(q, sample, m.dims, threads=cores)
+    dt = time.perf_counter() - t0
+    got = gpu_words_fn(sample)
+    exact = bool(np.array_equal(got, want))
+    return {"value": n / dt, "unit": "tets/s", "cores": cores, "kind": "oracle",
+            "sample": f"first {n} of {m.nt} tets (snap + voxelize, {dt:.1f} s wall)",
+            "seconds": dt, "gpu_bit_exact_on_sample": exact}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="large", choices=["large", "medium", "small"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on exactly one GPU: the voxelizer is a single-GPU build "
+              "(multi-GPU sharding is a design note only); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2106_01326_amd as tv
+
+    if not torch.cuda.is_available():
+        raise SystemExit("no GPU visible")
+    tv.load_library()
+    log(f"generating workload {args.workload}")
+    t0 = time.perf_counter()
+    m = make_workload(args.workload)
+    log(f"generated nt={m.nt} nv={m.nv} in {time.perf_counter() - t0:.1f} s")
+
+    dev = torch.device("cuda:0")
+    qverts = m.verts is None
+    v = torch.from_numpy(m.qverts if qverts else m.verts).to(dev)
+    t = torch.from_numpy(m.tets).to(dev)
+    grid = tv.alloc_grid(m.dims, dev)
+    ws = tv.alloc_workspace(tv.workspace_bytes(m.nv, m.nt, m.dims), dev)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        tv.voxelize(v, t, m.dims, m.bbox, qverts=qverts, grid=grid, workspace=ws, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    assert tv.fetch_status(ws) == tv.TV_OK
+    log(f"warmup done ({args.warmup} steps)")
+
+    tv.profile_read()  # drop anything recorded before
+    tv.profile_enable(True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    tv.profile_enable(False)
+    stages, calls = tv.profile_read()
+    ms_total = ev0.elapsed_time(ev1)
+    ms_step = ms_total / args.steps
+    log(f"timed {args.steps} steps: {ms_step:.4f} ms/step; stages {stages}")
+
+    q_lat = m.qverts if qverts else tv.snap(v, m.bbox).cpu().numpy()
+    n_nonempty, n_cols, n_cand = candidate_work(q_lat, m.tets, m.dims)
+    words = grid.cpu().numpy().view(np.uint32)
+    n_set = int(np.unpackbits(words.view(np.uint8)).sum())
+
+    vox_ms = stages.get("voxelize", 0.0) / max(calls, 1)
+    ops = SETUP_OPS_PER_TET * n_nonempty + OPS_PER_COLUMN * n_cols
+    achieved = ops / (vox_ms * 1e-3) / 1e12 if vox_ms > 0 else None
+    roofline = {"bound": "alu", "kernel": "k_tile_voxelize", "achieved": achieved,
+                "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
+                "frac": (achieved / VALU_PEAK_TOPS) if achieved else None,
+                "traffic": traffic_from_profiles(args.workload),
+                "kernel_ms": vox_ms, "ops_per_launch": ops,
+                "units": {"tets_nonempty": n_nonempty, "candidate_columns": n_cols,
+                          "candidate_centers": n_cand}}
+
+    out = {"metric": "tets voxelized/s", "value": m.nt / (ms_step * 1e-3), "unit": "tets/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic (seeded jittered Kuhn meshes)",
+           "config": workload_config(args.workload, m),
+           "meshes_per_s": 1e3 / ms_step, "voxels_set_per_s": n_set / (ms_step * 1e-3),
+           "stage_ms": {k: v_ / max(calls, 1) for k, v_ in stages.items()},
+           "roofline": roofline}
+
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle on a bounded sample)")
+
+        def gpu_words(sample):
+            ts = torch.from_numpy(np.ascontiguousarray(sample)).to(dev)
+            g2, w2 = tv.voxelize(v, ts, m.dims, m.bbox, qverts=qverts)
+            torch.cuda.synchronize()
+            return g2.cpu().numpy().view(np.uint32)
+
+        out["cpu_baseline"] = cpu_baseline(m, gpu_words, args.cpu_seconds)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -72,6 +72,8 @@ typedef int32_t tv_status;
 /* flags */
 #define TV_TIE_HALF_OPEN 0u /* default tie rule (see above) */
 #define TV_TIE_STRICT 1u    /* Theorem 1 literally: a center on a face is outside */
+#define TV_PATH_PER_TET 2u  /* reference path: one lane per tet, word atomics into a
+                               cleared grid (same output, slower; for A/B checks) */
 
 typedef struct {
     int32_t nx, ny, nz; /* each a power of two in [1, 32768] */
@@ -84,13 +86,15 @@ typedef struct {
 /* Number of uint32 words of a grid: nx * ny * ceil(nz / 32).  0 for bad dims. */
 size_t tv_grid_words(tv_dims dims);
 
-/* Workspace bytes needed by tv_voxelize / tv_voxelize_q for these sizes. */
+/* Workspace bytes needed by tv_voxelize / tv_voxelize_q for these sizes
+ * (about 16 bytes per vertex plus 36 bytes per tet plus a few bytes per
+ * grid tile). */
 size_t tv_workspace_bytes(int64_t nv, int64_t nt, tv_dims dims, uint32_t flags);
 
 /*
  * Voxelize one mesh given fp32 world coordinates.
  *   verts  [nv][3] float32, device, row-major (x, y, z)
- *   tets   [nt][4] int32, device, vertex indices
+ *   tets   [nt][4] int32, device, vertex indices, 16-byte aligned
  *   dims   grid resolution; bbox: world box covered by the grid
  *   grid   [tv_grid_words(dims)] uint32, device, written entirely
  *   ws     workspace (device, 256-byte aligned, >= tv_workspace_bytes)
@@ -107,12 +111,33 @@ tv_status tv_voxelize_q(const int32_t *qverts, int64_t nv, const int32_t *tets, 
                         uint32_t flags);
 
 /*
+ * Snap only: fp32 world coordinates verts [nv][3] -> lattice coordinates
+ * q_out [nv][3] int32 (both device), per the snap rule above.  A vertex that
+ * is NaN or off the lattice range is written as three TV_Q_INVALID values.
+ * Asynchronous on `stream`; argument errors as for tv_voxelize.
+ */
+#define TV_Q_INVALID INT32_MIN
+tv_status tv_snap(const float *verts, int64_t nv, tv_bbox bbox, int32_t *q_out, void *stream);
+
+/*
  * Data-error status of mesh `mesh_index` recorded in workspace `ws` by the
  * last call that used it (index 0 for the single-mesh calls).  Synchronizes
  * `stream`, then returns TV_OK, TV_ERR_INDEX or TV_ERR_RANGE (TV_ERR_INDEX
  * wins when both occurred), or TV_ERR_INVALID_ARG / TV_ERR_HIP.
  */
 tv_status tv_fetch_status(const void *ws, int32_t mesh_index, void *stream);
+
+/*
+ * Diagnostics: per-stage timing with HIP events.  While enabled, every call
+ * records a start and an end event around each of its stages on its own
+ * stream.  tv_profile_read waits for those events, returns the summed
+ * milliseconds per stage (ms_out[stage], up to max_stages entries) and the
+ * number of calls recorded, then clears the record.  Process-wide state; not
+ * meant for concurrent callers.  Stage names: tv_profile_stage_name.
+ */
+tv_status tv_profile_enable(int32_t on);
+tv_status tv_profile_read(double *ms_out, int32_t max_stages, int32_t *n_stages, int64_t *n_calls);
+const char *tv_profile_stage_name(int32_t stage);
 
 /* Human-readable name of a status code (static storage). */
 const char *tv_status_string(tv_status s);

@@ -28,9 +28,12 @@ TV_ERR_HIP = -7
 
 TIE_HALF_OPEN = 0
 TIE_STRICT = 1
+PATH_PER_TET = 2
+Q_INVALID = -(1 << 31)
 
-EXPORTED = ("tv_grid_words", "tv_workspace_bytes", "tv_voxelize", "tv_voxelize_q",
-            "tv_fetch_status", "tv_status_string", "tv_last_error")
+EXPORTED = ("tv_grid_words", "tv_workspace_bytes", "tv_voxelize", "tv_voxelize_q", "tv_snap",
+            "tv_fetch_status", "tv_status_string", "tv_last_error", "tv_profile_enable",
+            "tv_profile_read", "tv_profile_stage_name")
 
 
 class Dims(ctypes.Structure):
@@ -75,12 +78,20 @@ def load_library():
     lib.tv_voxelize.restype = st
     lib.tv_voxelize_q.argtypes = [P, i64, P, i64, Dims, P, P, ctypes.c_size_t, P, u32]
     lib.tv_voxelize_q.restype = st
+    lib.tv_snap.argtypes = [P, i64, BBox, P, P]
+    lib.tv_snap.restype = st
     lib.tv_fetch_status.argtypes = [P, ctypes.c_int32, P]
     lib.tv_fetch_status.restype = st
     lib.tv_status_string.argtypes = [st]
     lib.tv_status_string.restype = ctypes.c_char_p
     lib.tv_last_error.argtypes = []
     lib.tv_last_error.restype = ctypes.c_char_p
+    lib.tv_profile_enable.argtypes = [ctypes.c_int32]
+    lib.tv_profile_enable.restype = st
+    lib.tv_profile_read.argtypes = [P, ctypes.c_int32, P, P]
+    lib.tv_profile_read.restype = st
+    lib.tv_profile_stage_name.argtypes = [ctypes.c_int32]
+    lib.tv_profile_stage_name.restype = ctypes.c_char_p
     _lib = lib
     return lib
 
@@ -148,19 +159,25 @@ def alloc_grid(dims, device=None):
                        device=device if device is not None else "cuda")
 
 
-def voxelize(verts, tets, dims, bbox=None, *, qverts=False, strict=False, grid=None,
+def _bbox(bbox) -> BBox:
+    lo, hi = bbox
+    return BBox((ctypes.c_float * 3)(*[float(x) for x in lo]), (ctypes.c_float * 3)(*[float(x) for x in hi]))
+
+
+def voxelize(verts, tets, dims, bbox=None, *, qverts=False, strict=False, per_tet=False, grid=None,
              workspace=None, stream=None):
     """Voxelize one mesh on the GPU (asynchronous on ``stream``).
 
     verts: [nv,3] float32 world coordinates (``qverts=False``, needs ``bbox``
     = (lo[3], hi[3])) or [nv,3] int32 lattice coordinates (``qverts=True``).
-    tets: [nt,4] int32.  Returns (grid, workspace); call ``fetch_status`` on
-    the workspace to read device-side data errors.
+    tets: [nt,4] int32.  ``per_tet`` selects the reference path.  Returns
+    (grid, workspace); call ``fetch_status`` on the workspace to read
+    device-side data errors.
     """
     lib = load_library()
     torch = _torch()
     d = _dims(dims)
-    flags = TIE_STRICT if strict else TIE_HALF_OPEN
+    flags = (TIE_STRICT if strict else TIE_HALF_OPEN) | (PATH_PER_TET if per_tet else 0)
     vptr, nv = _dev_ptr(verts, torch.int32 if qverts else torch.float32, 3, "verts")
     tptr, nt = _dev_ptr(tets, torch.int32, 4, "tets")
     if grid is None:
@@ -178,11 +195,22 @@ def voxelize(verts, tets, dims, bbox=None, *, qverts=False, strict=False, grid=N
     else:
         if bbox is None:
             raise ValueError("fp32 vertices need a bbox")
-        lo, hi = bbox
-        b = BBox((ctypes.c_float * 3)(*[float(x) for x in lo]), (ctypes.c_float * 3)(*[float(x) for x in hi]))
-        rc = lib.tv_voxelize(vptr, nv, tptr, nt, d, b, gptr, wptr, workspace.numel(), s, flags)
+        rc = lib.tv_voxelize(vptr, nv, tptr, nt, d, _bbox(bbox), gptr, wptr, workspace.numel(), s, flags)
     _check(rc)
     return grid, workspace
+
+
+def snap(verts, bbox, out=None, stream=None):
+    """fp32 world coordinates [nv,3] -> int32 lattice coordinates [nv,3] on
+    the device (bad vertices come back as Q_INVALID)."""
+    lib = load_library()
+    torch = _torch()
+    vptr, nv = _dev_ptr(verts, torch.float32, 3, "verts")
+    if out is None:
+        out = torch.empty((nv, 3), dtype=torch.int32, device=verts.device)
+    optr, _ = _dev_ptr(out, torch.int32, 3, "out")
+    _check(lib.tv_snap(vptr, nv, _bbox(bbox), optr, _stream_handle(stream)))
+    return out
 
 
 def fetch_status(workspace, mesh_index: int = 0, stream=None) -> int:
@@ -191,3 +219,21 @@ def fetch_status(workspace, mesh_index: int = 0, stream=None) -> int:
     torch = _torch()
     wptr, _ = _dev_ptr(workspace, torch.uint8, None, "workspace")
     return int(lib.tv_fetch_status(wptr, int(mesh_index), _stream_handle(stream)))
+
+
+def profile_enable(on: bool = True):
+    """Enable/disable per-stage HIP-event timing of subsequent calls."""
+    _check(load_library().tv_profile_enable(1 if on else 0))
+
+
+def profile_read() -> tuple[dict, int]:
+    """Summed milliseconds per stage since the last read, and the call count
+    (waits for the recorded events)."""
+    lib = load_library()
+    ms = (ctypes.c_double * 16)()
+    n = ctypes.c_int32(0)
+    calls = ctypes.c_int64(0)
+    _check(lib.tv_profile_read(ctypes.cast(ms, ctypes.c_void_p), 16, ctypes.cast(ctypes.pointer(n), ctypes.c_void_p),
+                               ctypes.cast(ctypes.pointer(calls), ctypes.c_void_p)))
+    out = {lib.tv_profile_stage_name(i).decode(): ms[i] for i in range(n.value)}
+    return out, int(calls.value)

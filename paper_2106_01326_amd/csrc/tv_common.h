@@ -6,9 +6,9 @@
 // of edge vectors) have components below 2 * (2^16.59)^2 = 2^34.17, and a
 // face function n . (P - U) at any voxel center P (P in [0, 2^16] per axis,
 // so |P - U| <= 1.25 * 2^16 = 2^16.33) is below 3 * 2^34.17 * 2^16.33 =
-// 2^52.09 in magnitude.  Every partial sum and product below therefore stays under
-// 2^53 and is exact in IEEE double, which gfx950 executes at full rate; the
-// double type is used as an exact 53-bit integer carrier, never for a
+// 2^52.09 in magnitude.  Every partial sum and product below therefore stays
+// under 2^53 and is exact in IEEE double, which gfx950 executes at full rate;
+// the double type is used as an exact 53-bit integer carrier, never for a
 // rounded quantity, except the quotient estimates that are always followed
 // by an exact integer fix-up.
 #pragma once
@@ -33,6 +33,10 @@ struct GridGeom {
     int32_t words;     // W = ceil(nz / 32) words per column
 };
 
+__device__ __forceinline__ bool index_ok(int32_t x, int64_t nv) {
+    return x >= 0 && (int64_t)x < nv;
+}
+
 // Candidate index range of one axis: voxel centers (2i+1)S with
 // lo <= (2i+1)S <= hi, clipped to [0, n-1].  The pitch 2S is a power of two,
 // so floor/ceil division are arithmetic shifts (all values fit in int32).
@@ -44,6 +48,19 @@ __device__ __forceinline__ void axis_range(int32_t lo, int32_t hi, int32_t half,
     i1 = i1 > n - 1 ? n - 1 : i1;
 }
 
+// Candidate box of a tet (inclusive voxel index ranges); false when empty.
+__device__ __forceinline__ bool candidate_box(const int4 &A, const int4 &B, const int4 &C,
+                                              const int4 &D, const GridGeom &g, int32_t lo[3],
+                                              int32_t hi[3]) {
+    const int32_t mn[3] = {min(min(A.x, B.x), min(C.x, D.x)), min(min(A.y, B.y), min(C.y, D.y)),
+                           min(min(A.z, B.z), min(C.z, D.z))};
+    const int32_t mx[3] = {max(max(A.x, B.x), max(C.x, D.x)), max(max(A.y, B.y), max(C.y, D.y)),
+                           max(max(A.z, B.z), max(C.z, D.z))};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) axis_range(mn[a], mx[a], g.half[a], g.shift[a], g.n[a], lo[a], hi[a]);
+    return lo[0] <= hi[0] && lo[1] <= hi[1] && lo[2] <= hi[2];
+}
+
 // The half-open tie rule: a face function that is exactly zero at a center
 // counts as positive iff its gradient is lexicographically positive in the
 // order (z, y, x) -- the sign it takes after the push eps*ez + eps^2*ey +
@@ -52,32 +69,47 @@ __device__ __forceinline__ bool lex_positive(double gx, double gy, double gz) {
     return gz > 0.0 || (gz == 0.0 && (gy > 0.0 || (gy == 0.0 && gx > 0.0)));
 }
 
-// Per-face data of one tet, relative to the center of the first candidate
-// voxel (i0, j0, k0).  For candidate (i0+di, j0+dj, k0+dk) the center is
-// inside this face's half-space iff
-//     base + sx*di + sy*dj + sz*dk >= 0
-// where base already folds in the tie rule (-1 when a zero must count as
-// outside).  All values are exact integers held in doubles.
+// One face of a tet in "threshold form", relative to the first candidate
+// center (i0, j0, k0) of a box.  For the column (i0+di, j0+dj):
+//     a(di, dj) = A + SX*di + SY*dj
+// and the face admits dk exactly for dk >= t or dk < t (see lower), where
+// t is the smallest integer dk >= 0 with a + S*dk >= 0 (t = ceil(-a/S)).
+// Lower faces (gradient z > 0, and vertical faces) give the span's start,
+// upper faces its end.  A vertical face (S = 0) stores R = 2^60 so that the
+// same formula yields t = 0 (whole column in) for a >= 0 and t = everything
+// for a < 0.  All values are exact integers held in doubles, except R.
 struct Face {
-    double base, sx, sy, sz, rinv;  // rinv = 1/|sz| (0 when sz == 0)
+    double A, SX, SY, S;
+    float R;  // estimate of 1/S (relative error <= 2^-24), or 2^60 when S = 0
 };
 
-// Builds the four inward faces of tet (A,B,C,D) (lattice coordinates) for
-// the candidate box whose first center is p0.  Returns false for a
-// degenerate tet.  The face opposite vertex X through (U,V,W) has normal
-// (V-U) x (W-U), flipped so that X lies on its positive side; its function
-// n . (P - U) is |6 vol| times X's barycentric coordinate at P, i.e. the
-// same affine function whose sign Theorem 1's determinant of that face
-// decides.
+// Builds the four faces of tet (A,B,C,D) (lattice coordinates) relative to
+// the voxel center p0.  Returns false for a degenerate tet.  lower_mask bit f
+// is set when face f bounds the span from below.
+//
+// The face opposite vertex X through (U,V,W) has normal (V-U) x (W-U),
+// flipped so that X lies on its positive side; L(P) = n . (P - U) is
+// |6 vol| times X's barycentric coordinate at P -- the affine function whose
+// sign Theorem 1's determinant of that face decides.  The center is on the
+// inner side iff L + c >= 0, with c = 0 when a zero counts as inside (tie
+// rule: n lexicographically positive; never in strict mode) and c = -1
+// otherwise.  Along a column L = L0 + sz*dk with sz = n_z * 2Sz:
+//   sz > 0 (lower face): admitted dk are those >= the first dk with
+//          (L0 + c) + sz*dk >= 0;
+//   sz < 0 (upper face): admitted dk are those below the first dk with
+//          L0 + c + sz*dk < 0, i.e. with (-L0 - c - 1) + (-sz)*dk >= 0;
+//   sz = 0 (vertical face): every dk or none, by the sign of L0 + c.
 __device__ __forceinline__ bool build_faces(const int4 &A, const int4 &B, const int4 &C,
                                             const int4 &D, const double p0[3],
-                                            const GridGeom &g, bool strict, Face f[4]) {
+                                            const GridGeom &g, bool strict, Face f[4],
+                                            uint32_t &lower_mask) {
     const double v[4][3] = {{(double)A.x, (double)A.y, (double)A.z},
                             {(double)B.x, (double)B.y, (double)B.z},
                             {(double)C.x, (double)C.y, (double)C.z},
                             {(double)D.x, (double)D.y, (double)D.z}};
     // (opposite vertex, three face vertices)
     const int tri[4][4] = {{0, 1, 2, 3}, {1, 0, 2, 3}, {2, 0, 1, 3}, {3, 0, 1, 2}};
+    lower_mask = 0;
 #pragma unroll
     for (int fi = 0; fi < 4; ++fi) {
         const double *X = v[tri[fi][0]], *U = v[tri[fi][1]], *V = v[tri[fi][2]],
@@ -88,51 +120,55 @@ __device__ __forceinline__ bool build_faces(const int4 &A, const int4 &B, const 
                        e1[0] * e2[1] - e1[1] * e2[0]};
         const double side = n[0] * (X[0] - U[0]) + n[1] * (X[1] - U[1]) + n[2] * (X[2] - U[2]);
         if (side == 0.0) return false;
-        if (side < 0.0) {
-            n[0] = -n[0];
-            n[1] = -n[1];
-            n[2] = -n[2];
+        const double o = side < 0.0 ? -1.0 : 1.0;
+        n[0] *= o;
+        n[1] *= o;
+        n[2] *= o;
+        // inside iff L + c >= 0, c = 0 when a zero counts as inside else -1
+        const double c = (!strict && lex_positive(n[0], n[1], n[2])) ? 0.0 : -1.0;
+        const double L0 =
+            n[0] * (p0[0] - U[0]) + n[1] * (p0[1] - U[1]) + n[2] * (p0[2] - U[2]) + c;
+        const double sx = n[0] * (double)(2 * g.half[0]);
+        const double sy = n[1] * (double)(2 * g.half[1]);
+        const double sz = n[2] * (double)(2 * g.half[2]);
+        if (sz >= 0.0) {
+            // lower (or vertical): span starts at the first dk with L0 + sz dk >= 0
+            f[fi].A = L0;
+            f[fi].SX = sx;
+            f[fi].SY = sy;
+            f[fi].S = sz;
+            f[fi].R = sz > 0.0 ? (float)(1.0 / sz) : 1152921504606846976.0f;  // 2^60
+            lower_mask |= 1u << fi;
+        } else {
+            // upper: span ends at the first dk with L0 + sz dk < 0, i.e. with
+            // -(L0 + sz dk) - 1 >= 0
+            f[fi].A = -L0 - 1.0;
+            f[fi].SX = -sx;
+            f[fi].SY = -sy;
+            f[fi].S = -sz;
+            f[fi].R = (float)(1.0 / (-sz));
         }
-        const double tie = (!strict && lex_positive(n[0], n[1], n[2])) ? 0.0 : -1.0;
-        f[fi].base = n[0] * (p0[0] - U[0]) + n[1] * (p0[1] - U[1]) + n[2] * (p0[2] - U[2]) + tie;
-        f[fi].sx = n[0] * (double)(2 * g.half[0]);
-        f[fi].sy = n[1] * (double)(2 * g.half[1]);
-        f[fi].sz = n[2] * (double)(2 * g.half[2]);
-        f[fi].rinv = f[fi].sz != 0.0 ? 1.0 / fabs(f[fi].sz) : 0.0;
     }
     return true;
 }
 
-// Narrows the z span [lo, hi) (box-relative, 0 <= lo, hi <= nk) of one column
-// by one face, given a = the face value at dk = 0 of this column.
-//   sz > 0: keep dk >= ceil(-a / sz)         (smallest dk with a + sz dk >= 0)
-//   sz < 0: keep dk <  floor(a / |sz|) + 1   (first dk with a + sz dk < 0)
-//   sz = 0: keep all or nothing (sign of a)
-// The quotient comes from a reciprocal estimate (relative error < 2^-51, so
-// off by at most one after clamping to [0, nk]) and is corrected by exact
-// evaluations of a + sz*dk at in-box dk.
-__device__ __forceinline__ void clip_span(const Face &f, double a, int32_t nk, int32_t &lo,
-                                          int32_t &hi) {
-    if (f.sz > 0.0) {
-        double e = ceil(-a * f.rinv);
-        e = fmin(fmax(e, 0.0), (double)nk);
-        int32_t k = (int32_t)e;
-        if (k > 0 && fma(f.sz, (double)(k - 1), a) >= 0.0) k -= 1;
-        else if (k < nk && fma(f.sz, (double)k, a) < 0.0) k += 1;
-        lo = k > lo ? k : lo;
-    } else if (f.sz < 0.0) {
-        double e = floor(a * f.rinv) + 1.0;
-        e = fmin(fmax(e, 0.0), (double)nk);
-        int32_t k = (int32_t)e;
-        if (k > 0 && fma(f.sz, (double)(k - 1), a) < 0.0) k -= 1;
-        else if (k < nk && fma(f.sz, (double)k, a) >= 0.0) k += 1;
-        hi = k < hi ? k : hi;
-    } else if (a < 0.0) {
-        hi = 0;
-    }
+// First dk in [0, nk] with a + S*dk >= 0 (nk when none in [0, nk-1]).
+// With x = -a/S the threshold is t = ceil(x).  The estimate
+// y = fma(-a, R, -1/2) has relative error below 2^-23 (R is 1/S rounded to
+// float), so for |x| <= 2^20 it lies in [x - 0.57, x - 0.43] and ceil(y) is
+// t or t - 1; for larger |x| (nk <= 2^15) y and x clamp to the same end of
+// [0, nk].  One exact evaluation of a + S*dk at an in-box dk fixes the
+// estimate.
+__device__ __forceinline__ int32_t face_threshold(const Face &f, double a, int32_t nk,
+                                                  double nkd) {
+    double e = ceil(fma(-a, (double)f.R, -0.5));
+    e = fmin(fmax(e, 0.0), nkd);
+    const bool up = (e < nkd) && (fma(f.S, e, a) < 0.0);
+    return (int32_t)e + (up ? 1 : 0);
 }
 
-// ORs the bit run [k_lo, k_hi) (global z indices, k_lo < k_hi) into one column.
+// ORs the bit run [k_lo, k_hi) (k_lo < k_hi, word-relative indices) into a
+// word array with device-scope atomics.
 __device__ __forceinline__ void or_run_global(uint32_t *col, int32_t k_lo, int32_t k_hi) {
     const int32_t w0 = k_lo >> 5, w1 = (k_hi - 1) >> 5;
     for (int32_t w = w0; w <= w1; ++w) {
@@ -140,6 +176,17 @@ __device__ __forceinline__ void or_run_global(uint32_t *col, int32_t k_lo, int32
         if (w == w0) m &= 0xffffffffu << (k_lo & 31);
         if (w == w1) m &= 0xffffffffu >> (31 - ((k_hi - 1) & 31));
         __hip_atomic_fetch_or(col + w, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Same for a word array in LDS.
+__device__ __forceinline__ void or_run_lds(uint32_t *col, int32_t k_lo, int32_t k_hi) {
+    const int32_t w0 = k_lo >> 5, w1 = (k_hi - 1) >> 5;
+    for (int32_t w = w0; w <= w1; ++w) {
+        uint32_t m = 0xffffffffu;
+        if (w == w0) m &= 0xffffffffu << (k_lo & 31);
+        if (w == w1) m &= 0xffffffffu >> (31 - ((k_hi - 1) & 31));
+        atomicOr(col + w, m);
     }
 }
 

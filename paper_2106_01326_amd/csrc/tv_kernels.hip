@@ -1,5 +1,21 @@
-// Device kernels of the single-mesh path: ingest (snap / range check),
-// grid clearing and the per-tet voxelization kernel.
+// Device kernels of the voxelizer: ingest (snap / range check), binning of
+// tets into grid tiles, the tile voxelization kernel, the large-tet kernel
+// and the per-tet reference kernel.
+//
+// Work decomposition.  The grid is cut into tiles of tx * ty columns and tw
+// words (32*tw voxels) of each column.  A tet meets the tiles that its
+// candidate box (the voxel centers inside its bounding box, Section 3
+// "Voxelization") overlaps; each (tet, tile) pair is a "piece".  Pieces are
+// counting-sorted by tile, and each tile's piece list is cut into chunks.
+// One workgroup takes one chunk: it builds the chunk's pieces' face data in
+// LDS, splits the pieces' columns into fixed-length strips so that all lanes
+// get equal work, decides every column's z span exactly and ORs it into a
+// tile bitmap in LDS.  A tile covered by one chunk is then written out with
+// plain stores (zeros included, so the grid needs no separate clear); a
+// tile covered by several chunks was zeroed beforehand and each chunk ORs
+// its non-zero words into it.  Tets whose candidate box meets more tiles
+// than a fixed cap are set aside and handled by a separate kernel that
+// spreads one tet's columns over a whole workgroup and ORs into the grid.
 #include "tv_common.h"
 #include "tv_kernels.h"
 
@@ -7,11 +23,23 @@ namespace tv {
 
 // ----------------------------------------------------------------- ingest
 
-// fp32 world coordinates -> lattice coordinates, per the snap contract:
+// fp32 world coordinate -> lattice coordinate, per the snap contract:
 // rint(((double)v - lo) * 65536 / (hi - lo)) evaluated left to right in IEEE
 // double (this file is built with -ffp-contract=off, and a subtraction
-// followed by a multiplication cannot be fused anyway).  The .w lane marks a
-// vertex that is NaN or off the lattice range; such vertices void their tets.
+// followed by a multiplication cannot be fused anyway).  Returns false for a
+// NaN or an off-range result.
+__device__ __forceinline__ bool snap_coord(float v, double lo, double ext, int32_t &q) {
+    double t = (double)v - lo;
+    t = t * 65536.0;
+    t = t / ext;
+    const double r = rint(t);
+    const bool in = (r >= (double)kQMin) && (r <= (double)kQMax);  // false for NaN
+    q = in ? (int32_t)r : 0;
+    return in;
+}
+
+// Snap into padded int4 records; the .w lane marks a vertex that is NaN or
+// off the lattice range -- such vertices void their tets.
 __global__ void k_ingest_f32(const float *__restrict__ v, int64_t nv, BoxD box,
                              int4 *__restrict__ q4, uint32_t *__restrict__ status) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -19,17 +47,22 @@ __global__ void k_ingest_f32(const float *__restrict__ v, int64_t nv, BoxD box,
     int32_t q[3];
     bool ok = true;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        double t = (double)v[3 * i + a] - box.lo[a];
-        t = t * 65536.0;
-        t = t / box.ext[a];
-        const double r = rint(t);
-        const bool in = (r >= (double)kQMin) && (r <= (double)kQMax);  // false for NaN
-        ok = ok && in;
-        q[a] = in ? (int32_t)r : 0;
-    }
+    for (int a = 0; a < 3; ++a) ok = snap_coord(v[3 * i + a], box.lo[a], box.ext[a], q[a]) && ok;
     q4[i] = make_int4(q[0], q[1], q[2], ok ? 0 : 1);
     if (!ok) atomicOr(status, kStatusRange);
+}
+
+// Snap into a plain [nv][3] int32 array (INT32_MIN marks a bad vertex).
+__global__ void k_snap_only(const float *__restrict__ v, int64_t nv, BoxD box,
+                            int32_t *__restrict__ q) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nv) return;
+    int32_t c[3];
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) ok = snap_coord(v[3 * i + a], box.lo[a], box.ext[a], c[a]) && ok;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) q[3 * i + a] = ok ? c[a] : INT32_MIN;
 }
 
 // int32 lattice coordinates -> padded int4 with the same range check.
@@ -44,74 +77,483 @@ __global__ void k_ingest_q32(const int32_t *__restrict__ qin, int64_t nv, int4 *
     if (!ok) atomicOr(status, kStatusRange);
 }
 
-// Zero `nwords` words at `p` (any 4-byte alignment) plus `nstatus` status
-// words.  A plain fill kernel rather than a memset node, so the same launch
-// sequence can be captured into a graph.
-__global__ void k_clear(uint32_t *__restrict__ p, int64_t nwords, uint32_t *__restrict__ st,
-                        int32_t nstatus) {
+// Zero `n` words at `p` (4-byte aligned) with 16-byte stores where possible.
+__global__ void k_clear(uint32_t *__restrict__ p, int64_t n) {
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    if (tid < nstatus) st[tid] = 0u;
-    // peel to 16-byte alignment
     const int64_t mis = (int64_t)(((uintptr_t)p >> 2) & 3);
-    const int64_t head = mis ? (4 - mis < nwords ? 4 - mis : nwords) : 0;
+    const int64_t head = mis ? (4 - mis < n ? 4 - mis : n) : 0;
     if (tid < head) p[tid] = 0u;
     uint4 *p4 = reinterpret_cast<uint4 *>(p + head);
-    const int64_t n4 = (nwords - head) >> 2;
+    const int64_t n4 = (n - head) >> 2;
     for (int64_t i = tid; i < n4; i += stride) p4[i] = make_uint4(0u, 0u, 0u, 0u);
     const int64_t tail0 = head + (n4 << 2);
-    if (tid < nwords - tail0) p[tail0 + tid] = 0u;
+    if (tid < n - tail0) p[tail0 + tid] = 0u;
 }
 
-// ------------------------------------------------- per-tet voxelization
+// ------------------------------------------------------------- tet gather
 
-// One lane per tet: gather its four lattice vertices, cull degenerate tets
-// and empty candidate boxes, then walk the (x, y) columns of the candidate
-// box; each column's z span comes from the four exact face bounds and is
-// ORed into the grid with word-level atomics.  The simplest form of the
-// bounding-box scan (Section 3, "Voxelization"); kept as an A/B reference
-// for the binned kernel.
+// Gathers tet t's vertices; false for a bad index (flagged in `status`
+// unless it is null) and for a vertex that failed ingest (flagged there).
+__device__ __forceinline__ bool gather_tet(const int4 *__restrict__ q4, int64_t nv,
+                                           const int4 *__restrict__ tets, int64_t t,
+                                           uint32_t *status, int4 V[4]) {
+    const int4 T = tets[t];
+    if (!index_ok(T.x, nv) || !index_ok(T.y, nv) || !index_ok(T.z, nv) || !index_ok(T.w, nv)) {
+        if (status) atomicOr(status, kStatusIndex);
+        return false;
+    }
+    V[0] = q4[T.x];
+    V[1] = q4[T.y];
+    V[2] = q4[T.z];
+    V[3] = q4[T.w];
+    return (V[0].w | V[1].w | V[2].w | V[3].w) == 0;
+}
+
+// Six times the signed volume (Lemma 1.1), exact in double (see tv_common.h).
+__device__ __forceinline__ double six_volume(const int4 V[4]) {
+    const double ax = V[1].x - V[0].x, ay = V[1].y - V[0].y, az = V[1].z - V[0].z;
+    const double bx = V[2].x - V[0].x, by = V[2].y - V[0].y, bz = V[2].z - V[0].z;
+    const double cx = V[3].x - V[0].x, cy = V[3].y - V[0].y, cz = V[3].z - V[0].z;
+    return ax * (by * cz - bz * cy) - ay * (bx * cz - bz * cx) + az * (bx * cy - by * cx);
+}
+
+struct TileRange {
+    int32_t x0, x1, y0, y1, z0, z1;  // inclusive tile index ranges
+};
+
+__device__ __forceinline__ TileRange tile_range(const int32_t lo[3], const int32_t hi[3],
+                                                const TilePlan &p) {
+    TileRange r;
+    r.x0 = lo[0] >> p.lx;
+    r.x1 = hi[0] >> p.lx;
+    r.y0 = lo[1] >> p.ly;
+    r.y1 = hi[1] >> p.ly;
+    r.z0 = lo[2] >> (5 + p.lw);
+    r.z1 = hi[2] >> (5 + p.lw);
+    return r;
+}
+
+__device__ __forceinline__ uint32_t tile_id(int32_t x, int32_t y, int32_t z, const TilePlan &p) {
+    return ((uint32_t)x * p.nty + y) * p.ntz + z;
+}
+
+// Wave-aggregated atomic add of 1 per active lane to counter[key]: lanes
+// sharing a key issue one atomic together.  Returns the old value plus the
+// lane's rank among the lanes with its key.
+__device__ __forceinline__ uint32_t aggregated_inc(uint32_t *counter, uint32_t key, bool active) {
+    const int lane = __lane_id();
+    uint64_t pending = __ballot(active);
+    uint32_t result = 0;
+    while (pending) {
+        const int leader = __ffsll((unsigned long long)pending) - 1;
+        const uint32_t lkey = __shfl(key, leader);
+        const uint64_t same = __ballot(active && key == lkey) & pending;
+        uint32_t old = 0;
+        if (lane == leader) old = atomicAdd(counter + lkey, (uint32_t)__popcll(same));
+        old = __shfl(old, leader);
+        if ((same >> lane) & 1ull) result = old + (uint32_t)__popcll(same & ((1ull << lane) - 1ull));
+        pending &= ~same;
+    }
+    return result;
+}
+
+// Shared front of both binning passes: the tet's tile range and piece
+// count (0 when it contributes nothing).
+__device__ __forceinline__ int32_t tet_pieces(const int4 *__restrict__ q4, int64_t nv,
+                                              const int4 *__restrict__ tets, int64_t t,
+                                              const GridGeom &g, const TilePlan &p,
+                                              uint32_t *status, TileRange &r) {
+    int4 V[4];
+    if (!gather_tet(q4, nv, tets, t, status, V)) return 0;
+    int32_t lo[3], hi[3];
+    if (!candidate_box(V[0], V[1], V[2], V[3], g, lo, hi)) return 0;
+    if (six_volume(V) == 0.0) return 0;
+    r = tile_range(lo, hi, p);
+    return (r.x1 - r.x0 + 1) * (r.y1 - r.y0 + 1) * (r.z1 - r.z0 + 1);
+}
+
+// Pass 1: count pieces per tile; tets with more pieces than the cap go to
+// the large-tet list.
+__global__ void k_bin_count(const int4 *__restrict__ q4, int64_t nv, const int4 *__restrict__ tets,
+                            int64_t nt, GridGeom g, TilePlan p, BinBuffers b) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    TileRange r = {0, -1, 0, -1, 0, -1};
+    int32_t np = 0;
+    if (t < nt) np = tet_pieces(q4, nv, tets, t, g, p, b.status, r);
+    const bool big = np > p.piece_cap;
+    if (big) {
+        const uint32_t slot = atomicAdd(&b.meta[kMetaBig], 1u);
+        b.big[slot] = (uint32_t)t;
+        np = 0;
+    }
+    // lanes walk their pieces in lockstep so that neighbouring tets, which
+    // mostly share tiles, aggregate their increments
+    const int32_t ny_ = r.y1 - r.y0 + 1, nz_ = r.z1 - r.z0 + 1;
+    int32_t maxp = np;
+    for (int off = 32; off > 0; off >>= 1) maxp = max(maxp, __shfl_xor(maxp, off));
+    for (int32_t k = 0; k < maxp; ++k) {
+        const bool act = k < np;
+        uint32_t key = 0;
+        if (act) {
+            const int32_t dz = k % nz_, rest = k / nz_;
+            const int32_t dy = rest % ny_, dx = rest / ny_;
+            key = tile_id(r.x0 + dx, r.y0 + dy, r.z0 + dz, p);
+        }
+        aggregated_inc(b.tile_count, key, act);
+    }
+}
+
+// Exclusive scan of the per-tile piece counts (one workgroup of 1024
+// threads, any tile count): tile_off[t] is the first piece slot of tile t;
+// chunk_off[t] the first chunk; meta[kMetaChunks] the chunk total.
+__global__ void __launch_bounds__(1024) k_scan_tiles(TilePlan p, BinBuffers b) {
+    __shared__ uint32_t s_cnt[1024], s_chk[1024];
+    __shared__ uint32_t s_base_cnt, s_base_chk;
+    const uint32_t nt = (uint32_t)p.ntiles;
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        s_base_cnt = 0;
+        s_base_chk = 0;
+    }
+    __syncthreads();
+    for (uint32_t base = 0; base < nt; base += 1024) {
+        const uint32_t i = base + tid;
+        const uint32_t c = i < nt ? b.tile_count[i] : 0u;
+        const uint32_t k = i < nt ? (c == 0 ? 1u : (c + p.chunk - 1) / p.chunk) : 0u;
+        s_cnt[tid] = c;
+        s_chk[tid] = k;
+        __syncthreads();
+        // Hillis-Steele inclusive scan
+        for (int off = 1; off < 1024; off <<= 1) {
+            const uint32_t a = tid >= off ? s_cnt[tid - off] : 0u;
+            const uint32_t d = tid >= off ? s_chk[tid - off] : 0u;
+            __syncthreads();
+            s_cnt[tid] += a;
+            s_chk[tid] += d;
+            __syncthreads();
+        }
+        if (i < nt) {
+            b.tile_off[i] = s_base_cnt + s_cnt[tid] - c;
+            b.chunk_off[i] = s_base_chk + s_chk[tid] - k;
+        }
+        __syncthreads();
+        if (tid == 1023) {
+            s_base_cnt += s_cnt[1023];
+            s_base_chk += s_chk[1023];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        b.tile_off[nt] = s_base_cnt;
+        b.chunk_off[nt] = s_base_chk;
+        b.meta[kMetaChunks] = s_base_chk;
+    }
+}
+
+// Pass 2: write every piece's tet id into its tile's slot range.
+__global__ void k_bin_scatter(const int4 *__restrict__ q4, int64_t nv,
+                              const int4 *__restrict__ tets, int64_t nt, GridGeom g, TilePlan p,
+                              BinBuffers b) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    TileRange r = {0, -1, 0, -1, 0, -1};
+    int32_t np = 0;
+    // status flags were raised by the counting pass already
+    if (t < nt) np = tet_pieces(q4, nv, tets, t, g, p, nullptr, r);
+    if (np > p.piece_cap) np = 0;
+    const int32_t ny_ = r.y1 - r.y0 + 1, nz_ = r.z1 - r.z0 + 1;
+    int32_t maxp = np;
+    for (int off = 32; off > 0; off >>= 1) maxp = max(maxp, __shfl_xor(maxp, off));
+    for (int32_t k = 0; k < maxp; ++k) {
+        const bool act = k < np;
+        uint32_t key = 0;
+        if (act) {
+            const int32_t dz = k % nz_, rest = k / nz_;
+            const int32_t dy = rest % ny_, dx = rest / ny_;
+            key = tile_id(r.x0 + dx, r.y0 + dy, r.z0 + dz, p);
+        }
+        const uint32_t rank = aggregated_inc(b.tile_cursor, key, act);
+        if (act) b.pieces[b.tile_off[key] + rank] = (uint32_t)t;
+    }
+}
+
+// Global word index of word w of tile-local column cl in tile `tile`.
+__device__ __forceinline__ int64_t tile_word(uint32_t tile, int32_t cl, int32_t w,
+                                             const GridGeom &g, const TilePlan &p) {
+    const int32_t tz = (int32_t)(tile % (uint32_t)p.ntz);
+    const uint32_t txy = tile / (uint32_t)p.ntz;
+    const int32_t ty = (int32_t)(txy % (uint32_t)p.nty), tx = (int32_t)(txy / (uint32_t)p.nty);
+    const int64_t i = ((int64_t)tx << p.lx) + (cl >> p.ly);
+    const int64_t j = ((int64_t)ty << p.ly) + (cl & ((1 << p.ly) - 1));
+    return (i * g.n[1] + j) * g.words + ((int64_t)tz << p.lw) + w;
+}
+
+// Zero the tiles that several chunks will OR into.
+__global__ void k_zero_shared_tiles(GridGeom g, TilePlan p, BinBuffers b, uint32_t *grid) {
+    const uint32_t tile = blockIdx.x;
+    if (tile >= (uint32_t)p.ntiles) return;
+    if (b.chunk_off[tile + 1] - b.chunk_off[tile] <= 1) return;
+    const int32_t tw = 1 << p.lw;
+    const int32_t nwords = (1 << (p.lx + p.ly)) * tw;
+    for (int32_t x = threadIdx.x; x < nwords; x += blockDim.x)
+        grid[tile_word(tile, x >> p.lw, x & (tw - 1), g, p)] = 0u;
+}
+
+// ------------------------------------------------------ tile voxelization
+
+constexpr int kTileThreads = 256;
+constexpr int kMaxTileWords = 8192;  // 32 KiB of LDS bitmap
+
+struct PieceRec {
+    Face f[4];
+    int16_t ci0, cj0;  // tile-local column origin of the clipped box
+    int16_t ni, nj;    // clipped box extent in columns
+    int16_t k0, nk;    // tile-local first z index and z extent
+    uint16_t lower;    // faces that start the span
+    uint16_t ncols;    // ni * nj (<= 1024)
+};
+
+// z span [lo, hi) (box-relative) of column (di, dj) of a piece.
+__device__ __forceinline__ void column_span(const Face f[4], uint32_t lower, double di, double dj,
+                                            int32_t nk, double nkd, int32_t &lo, int32_t &hi) {
+    lo = 0;
+    hi = nk;
+#pragma unroll
+    for (int fi = 0; fi < 4; ++fi) {
+        const double a = fma(f[fi].SY, dj, fma(f[fi].SX, di, f[fi].A));
+        const int32_t t = face_threshold(f[fi], a, nk, nkd);
+        const bool isl = (lower >> fi) & 1u;
+        lo = isl ? max(lo, t) : lo;
+        hi = isl ? hi : min(hi, t);
+    }
+}
+
+__global__ void __launch_bounds__(kTileThreads)
+    k_tile_voxelize(const int4 *__restrict__ q4, const int4 *__restrict__ tets, GridGeom g,
+                    TilePlan p, BinBuffers b, uint32_t *__restrict__ grid, int strict) {
+    __shared__ uint32_t s_bits[kMaxTileWords];
+    __shared__ PieceRec s_rec[kTileThreads];
+    __shared__ uint32_t s_soff[kTileThreads + 1];
+    __shared__ uint32_t s_chunk, s_tile, s_p0, s_p1, s_shared;
+
+    const int tid = threadIdx.x;
+    const int32_t tw = 1 << p.lw;
+    const int32_t tcols = 1 << (p.lx + p.ly);
+    const int32_t nwords = tcols * tw;
+    const int32_t strip = p.strip;
+    const uint32_t total = b.meta[kMetaChunks];
+
+    for (;;) {
+        if (tid == 0) {
+            const uint32_t c = atomicAdd(&b.meta[kMetaQueue], 1u);
+            s_chunk = c;
+            if (c < total) {
+                // tile = last t with chunk_off[t] <= c
+                uint32_t lo = 0, hi = (uint32_t)p.ntiles;  // invariant chunk_off[lo] <= c < chunk_off[hi]
+                while (hi - lo > 1) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (b.chunk_off[mid] <= c) lo = mid;
+                    else hi = mid;
+                }
+                const uint32_t k = c - b.chunk_off[lo];
+                const uint32_t nchunks = b.chunk_off[lo + 1] - b.chunk_off[lo];
+                const uint32_t pb = b.tile_off[lo], pe = b.tile_off[lo + 1];
+                s_tile = lo;
+                s_p0 = min(pe, pb + k * (uint32_t)p.chunk);
+                s_p1 = min(pe, pb + (k + 1) * (uint32_t)p.chunk);
+                s_shared = nchunks > 1 ? 1u : 0u;
+            }
+        }
+        __syncthreads();
+        if (s_chunk >= total) break;
+        const uint32_t tile = s_tile, p0 = s_p0, p1 = s_p1;
+        for (int32_t x = tid; x < nwords; x += kTileThreads) s_bits[x] = 0u;
+
+        // tile origin in voxel indices
+        const int32_t tz = (int32_t)(tile % (uint32_t)p.ntz);
+        const uint32_t txy = tile / (uint32_t)p.ntz;
+        const int32_t ty = (int32_t)(txy % (uint32_t)p.nty), tx = (int32_t)(txy / (uint32_t)p.nty);
+        const int32_t ti0 = tx << p.lx, tj0 = ty << p.ly, tk0 = tz << (p.lw + 5);
+        const int32_t ti1 = ti0 + (1 << p.lx) - 1, tj1 = tj0 + (1 << p.ly) - 1;
+        const int32_t tk1 = min(tk0 + (tw << 5) - 1, g.n[2] - 1);
+
+        for (uint32_t pb = p0; pb < p1; pb += kTileThreads) {
+            // phase 1: one lane per piece -> record in LDS
+            uint32_t nstrips = 0;
+            const uint32_t pi = pb + tid;
+            if (pi < p1) {
+                const uint32_t t = b.pieces[pi];
+                const int4 T = tets[t];
+                const int4 A = q4[T.x], B = q4[T.y], C = q4[T.z], D = q4[T.w];
+                int32_t lo[3], hi[3];
+                candidate_box(A, B, C, D, g, lo, hi);
+                lo[0] = max(lo[0], ti0);
+                hi[0] = min(hi[0], ti1);
+                lo[1] = max(lo[1], tj0);
+                hi[1] = min(hi[1], tj1);
+                lo[2] = max(lo[2], tk0);
+                hi[2] = min(hi[2], tk1);
+                PieceRec &R = s_rec[tid];
+                if (lo[0] <= hi[0] && lo[1] <= hi[1] && lo[2] <= hi[2]) {
+                    const double p0d[3] = {(double)((2 * lo[0] + 1) * g.half[0]),
+                                           (double)((2 * lo[1] + 1) * g.half[1]),
+                                           (double)((2 * lo[2] + 1) * g.half[2])};
+                    Face f[4];
+                    uint32_t lower;
+                    if (build_faces(A, B, C, D, p0d, g, strict != 0, f, lower)) {
+#pragma unroll
+                        for (int fi = 0; fi < 4; ++fi) R.f[fi] = f[fi];
+                        R.ci0 = (int16_t)(lo[0] - ti0);
+                        R.cj0 = (int16_t)(lo[1] - tj0);
+                        R.ni = (int16_t)(hi[0] - lo[0] + 1);
+                        R.nj = (int16_t)(hi[1] - lo[1] + 1);
+                        R.k0 = (int16_t)(lo[2] - tk0);
+                        R.nk = (int16_t)(hi[2] - lo[2] + 1);
+                        R.lower = (uint16_t)lower;
+                        R.ncols = (uint16_t)(R.ni * R.nj);
+                        nstrips = ((uint32_t)R.ncols + strip - 1) / strip;
+                    }
+                }
+            }
+            // phase 2: exclusive scan of strip counts (wave scan + wave sums)
+            s_soff[tid] = nstrips;
+            __syncthreads();
+            if (tid < 64) {
+                // 4 waves x 64 lanes: each of the first 64 threads scans 4 entries
+                uint32_t v0 = s_soff[4 * tid], v1 = s_soff[4 * tid + 1], v2 = s_soff[4 * tid + 2],
+                         v3 = s_soff[4 * tid + 3];
+                const uint32_t sum = v0 + v1 + v2 + v3;
+                uint32_t incl = sum;
+                for (int off = 1; off < 64; off <<= 1) {
+                    const uint32_t o = __shfl_up(incl, off);
+                    if (tid >= off) incl += o;
+                }
+                const uint32_t excl = incl - sum;
+                s_soff[4 * tid] = excl;
+                s_soff[4 * tid + 1] = excl + v0;
+                s_soff[4 * tid + 2] = excl + v0 + v1;
+                s_soff[4 * tid + 3] = excl + v0 + v1 + v2;
+                if (tid == 63) s_soff[kTileThreads] = incl;
+            }
+            __syncthreads();
+            // phase 3: strips of `strip` columns, one per lane
+            const uint32_t nst = s_soff[kTileThreads];
+            for (uint32_t s = tid; s < nst; s += kTileThreads) {
+                int32_t lo_r = 0, hi_r = kTileThreads;  // s_soff[lo_r] <= s < s_soff[hi_r]
+                while (hi_r - lo_r > 1) {
+                    const int32_t mid = (lo_r + hi_r) >> 1;
+                    if (s_soff[mid] <= s) lo_r = mid;
+                    else hi_r = mid;
+                }
+                const PieceRec &R = s_rec[lo_r];
+                Face f[4];
+#pragma unroll
+                for (int fi = 0; fi < 4; ++fi) f[fi] = R.f[fi];
+                const uint32_t lower = R.lower;
+                const int32_t nj = R.nj, nk = R.nk, k0 = R.k0, ci0 = R.ci0, cj0 = R.cj0;
+                const double nkd = (double)nk;
+                const uint32_t c0 = (s - s_soff[lo_r]) * (uint32_t)strip;
+                const uint32_t c1 = min(c0 + (uint32_t)strip, (uint32_t)R.ncols);
+                int32_t di = (int32_t)(c0 / (uint32_t)nj);
+                int32_t dj = (int32_t)(c0 - (uint32_t)di * (uint32_t)nj);
+                for (uint32_t c = c0; c < c1; ++c) {
+                    int32_t lo, hi;
+                    column_span(f, lower, (double)di, (double)dj, nk, nkd, lo, hi);
+                    if (lo < hi)
+                        or_run_lds(s_bits + (((ci0 + di) << p.ly) + cj0 + dj) * tw, k0 + lo, k0 + hi);
+                    if (++dj == nj) {
+                        dj = 0;
+                        ++di;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+
+        // flush the tile: word x of the bitmap is word (x & (tw-1)) of
+        // tile-local column x >> lw
+        const bool shared_tile = s_shared != 0;
+        const int64_t zbase = tk0 >> 5;
+        for (int32_t x = tid; x < nwords; x += kTileThreads) {
+            const uint32_t wv = s_bits[x];
+            const int32_t cl = x >> p.lw;
+            const int64_t i = ti0 + (cl >> p.ly), j = tj0 + (cl & ((1 << p.ly) - 1));
+            const int64_t gw = (i * g.n[1] + j) * g.words + zbase + (x & (tw - 1));
+            if (!shared_tile) grid[gw] = wv;
+            else if (wv) __hip_atomic_fetch_or(grid + gw, wv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();
+    }
+}
+
+// --------------------------------------------------------- large tets
+
+// One workgroup per large tet (its candidate box meets more tiles than the
+// cap): the whole box's columns are spread over the workgroup and ORed into
+// the grid with word atomics.  Runs after the tile kernel.
+__global__ void __launch_bounds__(256)
+    k_large_tets(const int4 *__restrict__ q4, const int4 *__restrict__ tets, GridGeom g,
+                 BinBuffers b, uint32_t *__restrict__ grid, int strict) {
+    const uint32_t nbig = b.meta[kMetaBig];
+    for (uint32_t e = blockIdx.x; e < nbig; e += gridDim.x) {
+        const uint32_t t = b.big[e];
+        const int4 T = tets[t];
+        const int4 A = q4[T.x], B = q4[T.y], C = q4[T.z], D = q4[T.w];
+        int32_t lo[3], hi[3];
+        candidate_box(A, B, C, D, g, lo, hi);
+        const double p0[3] = {(double)((2 * lo[0] + 1) * g.half[0]),
+                              (double)((2 * lo[1] + 1) * g.half[1]),
+                              (double)((2 * lo[2] + 1) * g.half[2])};
+        Face f[4];
+        uint32_t lower;
+        if (!build_faces(A, B, C, D, p0, g, strict != 0, f, lower)) continue;
+        const uint32_t nj = (uint32_t)(hi[1] - lo[1] + 1);
+        const uint32_t ncols = (uint32_t)(hi[0] - lo[0] + 1) * nj;
+        const int32_t nk = hi[2] - lo[2] + 1;
+        const double nkd = (double)nk;
+        for (uint32_t c = threadIdx.x; c < ncols; c += blockDim.x) {
+            const uint32_t di = c / nj, dj = c - di * nj;
+            int32_t s0, s1;
+            column_span(f, lower, (double)di, (double)dj, nk, nkd, s0, s1);
+            if (s0 < s1) {
+                const int64_t col = (int64_t)(lo[0] + di) * g.n[1] + (lo[1] + dj);
+                or_run_global(grid + col * g.words, lo[2] + s0, lo[2] + s1);
+            }
+        }
+    }
+}
+
+// ------------------------------------------------- per-tet reference path
+
+// One lane per tet walks all columns of its candidate box and ORs each
+// column's span into the grid with word atomics.  The plainest form of the
+// bounding-box scan; kept as an A/B reference for the tile pipeline (the
+// grid must be cleared first).
 __global__ void k_voxelize_per_tet(const int4 *__restrict__ q4, int64_t nv,
                                    const int4 *__restrict__ tets, int64_t nt, GridGeom g,
                                    uint32_t *__restrict__ grid, uint32_t *__restrict__ status,
                                    int strict) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nt) return;
-    const int4 T = tets[t];
-    if (!index_ok(T.x, nv) || !index_ok(T.y, nv) || !index_ok(T.z, nv) || !index_ok(T.w, nv)) {
-        atomicOr(status, kStatusIndex);
-        return;
-    }
-    const int4 A = q4[T.x], B = q4[T.y], C = q4[T.z], D = q4[T.w];
-    if (A.w | B.w | C.w | D.w) return;  // a vertex failed ingest (already flagged)
-
+    int4 V[4];
+    if (!gather_tet(q4, nv, tets, t, status, V)) return;
     int32_t lo[3], hi[3];
-    const int32_t mn[3] = {min(min(A.x, B.x), min(C.x, D.x)), min(min(A.y, B.y), min(C.y, D.y)),
-                           min(min(A.z, B.z), min(C.z, D.z))};
-    const int32_t mx[3] = {max(max(A.x, B.x), max(C.x, D.x)), max(max(A.y, B.y), max(C.y, D.y)),
-                           max(max(A.z, B.z), max(C.z, D.z))};
-#pragma unroll
-    for (int a = 0; a < 3; ++a) axis_range(mn[a], mx[a], g.half[a], g.shift[a], g.n[a], lo[a], hi[a]);
-    if (lo[0] > hi[0] || lo[1] > hi[1] || lo[2] > hi[2]) return;
-
+    if (!candidate_box(V[0], V[1], V[2], V[3], g, lo, hi)) return;
     const double p0[3] = {(double)((2 * lo[0] + 1) * g.half[0]),
                           (double)((2 * lo[1] + 1) * g.half[1]),
                           (double)((2 * lo[2] + 1) * g.half[2])};
     Face f[4];
-    if (!build_faces(A, B, C, D, p0, g, strict != 0, f)) return;
-
+    uint32_t lower;
+    if (!build_faces(V[0], V[1], V[2], V[3], p0, g, strict != 0, f, lower)) return;
     const int32_t ni = hi[0] - lo[0] + 1, nj = hi[1] - lo[1] + 1, nk = hi[2] - lo[2] + 1;
+    const double nkd = (double)nk;
     for (int32_t di = 0; di < ni; ++di) {
         for (int32_t dj = 0; dj < nj; ++dj) {
-            int32_t klo = 0, khi = nk;
-#pragma unroll
-            for (int fi = 0; fi < 4; ++fi) {
-                const double a = fma(f[fi].sy, (double)dj, fma(f[fi].sx, (double)di, f[fi].base));
-                clip_span(f[fi], a, nk, klo, khi);
-            }
-            if (klo < khi) {
+            int32_t s0, s1;
+            column_span(f, lower, (double)di, (double)dj, nk, nkd, s0, s1);
+            if (s0 < s1) {
                 const int64_t col = (int64_t)(lo[0] + di) * g.n[1] + (lo[1] + dj);
-                or_run_global(grid + col * g.words, lo[2] + klo, lo[2] + khi);
+                or_run_global(grid + col * g.words, lo[2] + s0, lo[2] + s1);
             }
         }
     }
@@ -133,11 +575,47 @@ void launch_ingest_q32(const int32_t *q, int64_t nv, int4 *q4, uint32_t *status,
     if (nv > 0) k_ingest_q32<<<blocks_for(nv), kBlock, 0, s>>>(q, nv, q4, status);
 }
 
-void launch_clear(uint32_t *p, int64_t nwords, uint32_t *status, int32_t nstatus, hipStream_t s) {
+void launch_snap_only(const float *v, int64_t nv, const BoxD &box, int32_t *q, hipStream_t s) {
+    if (nv > 0) k_snap_only<<<blocks_for(nv), kBlock, 0, s>>>(v, nv, box, q);
+}
+
+void launch_clear(uint32_t *p, int64_t nwords, hipStream_t s) {
+    if (nwords <= 0) return;
     int64_t want = (nwords / 4 + kBlock - 1) / kBlock;
     if (want < 1) want = 1;
     if (want > 8192) want = 8192;
-    k_clear<<<(unsigned)want, kBlock, 0, s>>>(p, nwords, status, nstatus);
+    k_clear<<<(unsigned)want, kBlock, 0, s>>>(p, nwords);
+}
+
+void launch_bin_count(const int4 *q4, int64_t nv, const int4 *tets, int64_t nt, const GridGeom &g,
+                      const TilePlan &p, const BinBuffers &b, hipStream_t s) {
+    if (nt > 0) k_bin_count<<<blocks_for(nt), kBlock, 0, s>>>(q4, nv, tets, nt, g, p, b);
+}
+
+void launch_scan_tiles(const TilePlan &p, const BinBuffers &b, hipStream_t s) {
+    k_scan_tiles<<<1, 1024, 0, s>>>(p, b);
+}
+
+void launch_bin_scatter(const int4 *q4, int64_t nv, const int4 *tets, int64_t nt,
+                        const GridGeom &g, const TilePlan &p, const BinBuffers &b, hipStream_t s) {
+    if (nt > 0) k_bin_scatter<<<blocks_for(nt), kBlock, 0, s>>>(q4, nv, tets, nt, g, p, b);
+}
+
+void launch_zero_shared_tiles(const GridGeom &g, const TilePlan &p, const BinBuffers &b,
+                              uint32_t *grid, hipStream_t s) {
+    k_zero_shared_tiles<<<(unsigned)p.ntiles, kBlock, 0, s>>>(g, p, b, grid);
+}
+
+void launch_tile_voxelize(const int4 *q4, const int4 *tets, const GridGeom &g, const TilePlan &p,
+                          const BinBuffers &b, uint32_t *grid, bool strict, int workgroups,
+                          hipStream_t s) {
+    k_tile_voxelize<<<(unsigned)workgroups, kTileThreads, 0, s>>>(q4, tets, g, p, b, grid,
+                                                                   strict ? 1 : 0);
+}
+
+void launch_large_tets(const int4 *q4, const int4 *tets, const GridGeom &g, const BinBuffers &b,
+                       uint32_t *grid, bool strict, int workgroups, hipStream_t s) {
+    k_large_tets<<<(unsigned)workgroups, 256, 0, s>>>(q4, tets, g, b, grid, strict ? 1 : 0);
 }
 
 void launch_voxelize_per_tet(const int4 *q4, int64_t nv, const int4 *tets, int64_t nt,
@@ -147,5 +625,7 @@ void launch_voxelize_per_tet(const int4 *q4, int64_t nv, const int4 *tets, int64
         k_voxelize_per_tet<<<blocks_for(nt), kBlock, 0, s>>>(q4, nv, tets, nt, g, grid, status,
                                                              strict ? 1 : 0);
 }
+
+int tile_max_words() { return kMaxTileWords; }
 
 }  // namespace tv

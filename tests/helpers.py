@@ -35,31 +35,40 @@ def to_numpy_words(grid) -> np.ndarray:
     return grid.cpu().numpy().view(np.uint32)
 
 
-def gpu_voxelize_mesh(mesh, strict=False, stream=None):
-    """Run the HIP path on a synth.Mesh; returns (uint32 words, status)."""
+def gpu_voxelize_mesh(mesh, strict=False, stream=None, per_tet=False, stale=True):
+    """Run the HIP path on a synth.Mesh; returns (uint32 words, status).
+    With ``stale`` the output grid starts filled with ones, so every word the
+    path fails to write shows up."""
     import torch
 
     import paper_2106_01326_amd as tv
 
     tets = torch.from_numpy(np.ascontiguousarray(mesh.tets)).cuda()
+    grid = tv.alloc_grid(mesh.dims)
+    if stale:
+        grid.fill_(-1)
     if mesh.verts is not None:
         v = torch.from_numpy(np.ascontiguousarray(mesh.verts)).cuda()
-        grid, ws = tv.voxelize(v, tets, mesh.dims, mesh.bbox, strict=strict, stream=stream)
+        grid, ws = tv.voxelize(v, tets, mesh.dims, mesh.bbox, strict=strict, per_tet=per_tet,
+                               grid=grid, stream=stream)
     else:
         v = torch.from_numpy(np.ascontiguousarray(mesh.qverts)).cuda()
-        grid, ws = tv.voxelize(v, tets, mesh.dims, qverts=True, strict=strict, stream=stream)
+        grid, ws = tv.voxelize(v, tets, mesh.dims, qverts=True, strict=strict, per_tet=per_tet,
+                               grid=grid, stream=stream)
     status = tv.fetch_status(ws, 0, stream)
     return to_numpy_words(grid), status
 
 
-def gpu_voxelize_q(q, tets, dims, strict=False):
+def gpu_voxelize_q(q, tets, dims, strict=False, per_tet=False):
     import torch
 
     import paper_2106_01326_amd as tv
 
     qt = torch.from_numpy(np.ascontiguousarray(q, dtype=np.int32)).cuda()
     tt = torch.from_numpy(np.ascontiguousarray(tets, dtype=np.int32)).cuda()
-    grid, ws = tv.voxelize(qt, tt, dims, qverts=True, strict=strict)
+    grid = tv.alloc_grid(dims)
+    grid.fill_(-1)
+    grid, ws = tv.voxelize(qt, tt, dims, qverts=True, strict=strict, per_tet=per_tet, grid=grid)
     return to_numpy_words(grid), tv.fetch_status(ws)
 
 

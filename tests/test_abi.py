@@ -40,7 +40,7 @@ def test_workspace_grows_with_vertices(lib):
     assert a >= 256 and b > a and b % 256 == 0
 
 
-def call_q(lib, nv=4, nt=1, dims=(8, 8, 8), grid=1, ws=256, ws_bytes=1 << 20, flags=0, tets=1, q=1):
+def call_q(lib, nv=4, nt=1, dims=(8, 8, 8), grid=256, ws=256, ws_bytes=1 << 20, flags=0, tets=256, q=256):
     d = tv.Dims(*dims)
     P = ctypes.c_void_p
     return lib.tv_voxelize_q(P(q), nv, P(tets), nt, d, P(grid), P(ws), ws_bytes, None, flags)
@@ -54,6 +54,7 @@ def test_host_argument_errors(lib):
     assert call_q(lib, grid=0) == tv.TV_ERR_INVALID_ARG
     assert call_q(lib, tets=0) == tv.TV_ERR_INVALID_ARG
     assert call_q(lib, flags=4) == tv.TV_ERR_INVALID_ARG
+    assert call_q(lib, tets=264) == tv.TV_ERR_INVALID_ARG  # tets not 16-byte aligned
     assert call_q(lib, ws=0) == tv.TV_ERR_WORKSPACE
     assert call_q(lib, ws=260) == tv.TV_ERR_WORKSPACE
     assert call_q(lib, ws_bytes=16) == tv.TV_ERR_WORKSPACE
@@ -61,7 +62,8 @@ def test_host_argument_errors(lib):
     d = tv.Dims(8, 8, 8)
     bad = tv.BBox((ctypes.c_float * 3)(0, 0, 0), (ctypes.c_float * 3)(1, 0, 1))
     P = ctypes.c_void_p
-    assert lib.tv_voxelize(P(1), 4, P(1), 1, d, bad, P(1), P(256), 1 << 20, None, 0) == tv.TV_ERR_INVALID_ARG
+    assert lib.tv_voxelize(P(256), 4, P(256), 1, d, bad, P(256), P(256), 1 << 20, None, 0) == tv.TV_ERR_INVALID_ARG
+    assert lib.tv_snap(P(256), 4, bad, P(256), None) == tv.TV_ERR_INVALID_ARG
     assert lib.tv_status_string(tv.TV_ERR_INDEX) == b"TV_ERR_INDEX"
 
 

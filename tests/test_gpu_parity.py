@@ -26,11 +26,12 @@ def assert_same(got, want, what):
     assert mm is None, f"{what}: first differing word {mm[0]} ({mm[1]} words differ)"
 
 
+@pytest.mark.parametrize("per_tet", [False, True])
 @pytest.mark.parametrize("strict", [False, True])
-def test_small_workload(oracle_mod, strict):
+def test_small_workload(oracle_mod, strict, per_tet):
     m = synth.workload_small()
-    banner(f"small workload nt={m.nt} strict={strict}")
-    got, st = gpu_voxelize_mesh(m, strict)
+    banner(f"small workload nt={m.nt} strict={strict} per_tet={per_tet}")
+    got, st = gpu_voxelize_mesh(m, strict, per_tet=per_tet)
     assert st == 0
     assert_same(got, oracle_words(oracle_mod, m, strict), "small")
 
@@ -178,25 +179,64 @@ def test_snap_matches_oracle_bit_exact(oracle_mod):
     got, st = gpu_voxelize_mesh(m)
     assert st == 0
     assert_same(got, oracle_mod.voxelize_q(q, tets, (64, 64, 64)), "snap probes")
-    # the snapped vertices themselves (int4 records right after the 256-byte
-    # status block of the single-mesh workspace)
+    # the snapped vertices themselves, through tv_snap
     import torch
 
     import paper_2106_01326_amd as tv
 
-    edge = np.array([[-16384 / LAT, 81920 / LAT, 0.5], [(2 * 77 + 1) / (2 * LAT), (2 * 78 + 1) / (2 * LAT), 1.0]],
-                    np.float32)
-    verts = np.concatenate([base, edge])
+    edge = np.array([[-16384 / LAT, 81920 / LAT, 0.5], [(2 * 77 + 1) / (2 * LAT), (2 * 78 + 1) / (2 * LAT), 1.0],
+                     [0.0, 1.0, 1.0 / 3.0]], np.float32)
     lo01, hi01 = np.zeros(3, np.float32), np.ones(3, np.float32)
     for b_lo, b_hi, vv in ((lo, hi, base), (lo01, hi01, edge)):
-        vt = torch.from_numpy(vv).cuda()
-        tt = torch.zeros((1, 4), dtype=torch.int32, device="cuda")
-        _, ws = tv.voxelize(vt, tt, (8, 8, 8), (b_lo, b_hi))
-        assert tv.fetch_status(ws) == 0
-        q4 = ws[256:256 + 16 * vv.shape[0]].cpu().numpy().view(np.int32).reshape(-1, 4)
-        assert np.array_equal(q4[:, :3], oracle_mod.snap(vv, b_lo, b_hi))
-        assert np.all(q4[:, 3] == 0)
-    del verts
+        q = tv.snap(torch.from_numpy(vv).cuda(), (b_lo, b_hi)).cpu().numpy()
+        assert np.array_equal(q, oracle_mod.snap(vv, b_lo, b_hi))
+    bad = np.array([[np.nan, 0, 0], [0.5, 0.5, 0.5], [0, 2.0, 0]], np.float32)
+    q = tv.snap(torch.from_numpy(bad).cuda(), (lo01, hi01)).cpu().numpy()
+    assert np.all(q[0] == tv.Q_INVALID) and np.all(q[2] == tv.Q_INVALID)
+    assert list(q[1]) == [32768, 32768, 32768]
+
+
+@pytest.mark.parametrize("per_tet", [False, True])
+def test_shared_tiles_and_chunks(oracle_mod, per_tet):
+    """Many tets per tile (a fine mesh in a coarse grid): tiles take several
+    chunks, are zeroed first and flushed with word atomics."""
+    m = synth.make_mesh(24, 0.35, 32, "ellipsoids", 3, 909)  # ~30k tets kept in one 32^3 tile
+    banner(f"shared tiles nt={m.nt}")
+    for dims in ((32, 32, 32), (16, 16, 64), (64, 64, 32)):
+        m.dims = dims
+        got, st = gpu_voxelize_mesh(m, per_tet=per_tet)
+        assert st == 0
+        assert_same(got, oracle_words(oracle_mod, m), f"shared tiles {dims}")
+
+
+@pytest.mark.parametrize("per_tet", [False, True])
+def test_large_tets_mixed_with_small(oracle_mod, per_tet):
+    """Tets whose candidate box meets more tiles than the cap go through the
+    large-tet kernel after the tile kernel; mixed with ordinary tets."""
+    rng = np.random.default_rng(1001)
+    small = synth.make_mesh(10, 0.3, 256, "ellipsoids", 2, 1002)
+    q_small = oracle_mod.snap(small.verts, *small.bbox)
+    big_q = np.array([[1000, 2000, 3000], [64000, 5000, 9000], [4000, 63000, 20000], [30000, 30000, 64000],
+                      [-16000, -16000, -16000], [81000, 40000, 100], [40000, 81000, 200], [40000, 40000, 81000]],
+                     np.int32)
+    q = np.concatenate([q_small, big_q])
+    n0 = q_small.shape[0]
+    big_t = np.array([[n0, n0 + 1, n0 + 2, n0 + 3], [n0 + 4, n0 + 5, n0 + 6, n0 + 7]], np.int32)
+    tets = np.concatenate([small.tets, big_t])
+    tets = tets[rng.permutation(tets.shape[0])]
+    for dims in ((256, 256, 256), (128, 512, 64)):
+        got, st = gpu_voxelize_q(q, tets, dims, per_tet=per_tet)
+        assert st == 0
+        assert_same(got, oracle_mod.voxelize_q(q, tets, dims), f"large tets {dims}")
+
+
+def test_random_tet_order(oracle_mod):
+    """Input order with no spatial coherence (the binning's aggregated
+    atomics see distinct keys in every lane)."""
+    m = synth.make_mesh(20, 0.4, 128, "ellipsoids", 4, 1003, shuffle=True)
+    got, st = gpu_voxelize_mesh(m)
+    assert st == 0
+    assert_same(got, oracle_words(oracle_mod, m), "shuffled")
 
 
 def test_repeatable_bit_identical():
@@ -219,9 +259,10 @@ def large():
     return synth.workload_large()
 
 
-def test_medium_workload_full_grid(oracle_mod, medium):
-    banner(f"medium workload nt={medium.nt} nv={medium.nv}")
-    got, st = gpu_voxelize_mesh(medium)
+@pytest.mark.parametrize("per_tet", [False, True])
+def test_medium_workload_full_grid(oracle_mod, medium, per_tet):
+    banner(f"medium workload nt={medium.nt} nv={medium.nv} per_tet={per_tet}")
+    got, st = gpu_voxelize_mesh(medium, per_tet=per_tet)
     assert st == 0
     assert_same(got, oracle_words(oracle_mod, medium), "medium")
 
