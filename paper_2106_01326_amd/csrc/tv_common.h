@@ -4,10 +4,11 @@
 // confined to the lattice range [-2^14, 2^16 + 2^14], so coordinate
 // differences are at most 1.5 * 2^16 < 2^16.59, face normals (cross products
 // of edge vectors) have components below 2 * (2^16.59)^2 = 2^34.17, and a
-// face function n . (P - U) at any voxel center P (P in [0, 2^16] per axis,
-// so |P - U| <= 1.25 * 2^16 = 2^16.33) is below 3 * 2^34.17 * 2^16.33 =
-// 2^52.09 in magnitude.  Every partial sum and product below therefore stays
-// under 2^53 and is exact in IEEE double, which gfx950 executes at full rate;
+// face function n . (P - U) at any voxel center P, or at the center one
+// voxel past the grid along z (P_z <= 1.5 * 2^16, so |P - U| <= 1.75 * 2^16
+// = 2^16.81), is below 3 * 2^34.17 * 2^16.81 = 2^52.56 in magnitude.  Every
+// partial sum and product below therefore stays under 2^53 and is exact in
+// IEEE double, which gfx950 executes at full rate;
 // the double type is used as an exact 53-bit integer carrier, never for a
 // rounded quantity, except the quotient estimates that are always followed
 // by an exact integer fix-up.
@@ -152,18 +153,17 @@ __device__ __forceinline__ bool build_faces(const int4 &A, const int4 &B, const 
     return true;
 }
 
-// First dk in [0, nk] with a + S*dk >= 0 (nk when none in [0, nk-1]).
-// With x = -a/S the threshold is t = ceil(x).  The estimate
+// First dk in [0, nk + 1] with a + S*dk >= 0 (at least nk when none in
+// [0, nk-1]).  With x = -a/S the threshold is t = ceil(x).  The estimate
 // y = fma(-a, R, -1/2) has relative error below 2^-23 (R is 1/S rounded to
 // float), so for |x| <= 2^20 it lies in [x - 0.57, x - 0.43] and ceil(y) is
 // t or t - 1; for larger |x| (nk <= 2^15) y and x clamp to the same end of
-// [0, nk].  One exact evaluation of a + S*dk at an in-box dk fixes the
-// estimate.
-__device__ __forceinline__ int32_t face_threshold(const Face &f, double a, int32_t nk,
-                                                  double nkd) {
+// [0, nk].  One exact evaluation of a + S*e at e <= nk (a center at most one
+// voxel past the box, still inside the exactness bound) fixes the estimate.
+__device__ __forceinline__ int32_t face_threshold(const Face &f, double a, double nkd) {
     double e = ceil(fma(-a, (double)f.R, -0.5));
     e = fmin(fmax(e, 0.0), nkd);
-    const bool up = (e < nkd) && (fma(f.S, e, a) < 0.0);
+    const bool up = fma(f.S, e, a) < 0.0;
     return (int32_t)e + (up ? 1 : 0);
 }
 

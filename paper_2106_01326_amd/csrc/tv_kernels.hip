@@ -138,26 +138,6 @@ __device__ __forceinline__ uint32_t tile_id(int32_t x, int32_t y, int32_t z, con
     return ((uint32_t)x * p.nty + y) * p.ntz + z;
 }
 
-// Wave-aggregated atomic add of 1 per active lane to counter[key]: lanes
-// sharing a key issue one atomic together.  Returns the old value plus the
-// lane's rank among the lanes with its key.
-__device__ __forceinline__ uint32_t aggregated_inc(uint32_t *counter, uint32_t key, bool active) {
-    const int lane = __lane_id();
-    uint64_t pending = __ballot(active);
-    uint32_t result = 0;
-    while (pending) {
-        const int leader = __ffsll((unsigned long long)pending) - 1;
-        const uint32_t lkey = __shfl(key, leader);
-        const uint64_t same = __ballot(active && key == lkey) & pending;
-        uint32_t old = 0;
-        if (lane == leader) old = atomicAdd(counter + lkey, (uint32_t)__popcll(same));
-        old = __shfl(old, leader);
-        if ((same >> lane) & 1ull) result = old + (uint32_t)__popcll(same & ((1ull << lane) - 1ull));
-        pending &= ~same;
-    }
-    return result;
-}
-
 // Shared front of both binning passes: the tet's tile range and piece
 // count (0 when it contributes nothing).
 __device__ __forceinline__ int32_t tet_pieces(const int4 *__restrict__ q4, int64_t nv,
@@ -173,34 +153,70 @@ __device__ __forceinline__ int32_t tet_pieces(const int4 *__restrict__ q4, int64
     return (r.x1 - r.x0 + 1) * (r.y1 - r.y0 + 1) * (r.z1 - r.z0 + 1);
 }
 
-// Pass 1: count pieces per tile; tets with more pieces than the cap go to
-// the large-tet list.
-__global__ void k_bin_count(const int4 *__restrict__ q4, int64_t nv, const int4 *__restrict__ tets,
-                            int64_t nt, GridGeom g, TilePlan p, BinBuffers b) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Both binning passes aggregate per workgroup: every piece's tile key goes
+// into an LDS hash table (open addressing, one slot per distinct key, an
+// LDS atomic gives the piece its rank among the workgroup's pieces of that
+// tile), then one global atomic per distinct key adds the workgroup's
+// count (pass 1) or reserves its slot range (pass 2).  Neighbouring tets,
+// which mostly share tiles, thus cost one global atomic per workgroup and
+// tile instead of one per piece.
+constexpr int kBinThreads = 256;
+constexpr int kHashSlots = 4096;  // >= 2 * kBinThreads * kPieceCapMax
+constexpr int kPieceCapMax = 8;
+constexpr uint32_t kEmptyKey = 0xffffffffu;
+
+__device__ __forceinline__ uint32_t hash_insert(uint32_t *keys, uint32_t key) {
+    uint32_t h = (key * 2654435761u) >> (32 - 12);
+    for (;;) {
+        const uint32_t prev = atomicCAS(keys + h, kEmptyKey, key);
+        if (prev == kEmptyKey || prev == key) return h;
+        h = (h + 1) & (kHashSlots - 1);
+    }
+}
+
+template <bool kScatter>
+__global__ void __launch_bounds__(kBinThreads)
+    k_bin(const int4 *__restrict__ q4, int64_t nv, const int4 *__restrict__ tets, int64_t nt,
+          GridGeom g, TilePlan p, BinBuffers b) {
+    __shared__ uint32_t s_key[kHashSlots];
+    __shared__ uint32_t s_cnt[kHashSlots];  // count, then (pass 2) global slot base
+    __shared__ uint32_t s_ref[kBinThreads * kPieceCapMax];  // slot << 16 | rank
+    const int tid = threadIdx.x;
+    for (int i = tid; i < kHashSlots; i += kBinThreads) {
+        s_key[i] = kEmptyKey;
+        s_cnt[i] = 0u;
+    }
+    __syncthreads();
+    const int64_t t = (int64_t)blockIdx.x * kBinThreads + tid;
     TileRange r = {0, -1, 0, -1, 0, -1};
     int32_t np = 0;
-    if (t < nt) np = tet_pieces(q4, nv, tets, t, g, p, b.status, r);
-    const bool big = np > p.piece_cap;
-    if (big) {
-        const uint32_t slot = atomicAdd(&b.meta[kMetaBig], 1u);
-        b.big[slot] = (uint32_t)t;
+    // status flags are raised by the counting pass only
+    if (t < nt) np = tet_pieces(q4, nv, tets, t, g, p, kScatter ? nullptr : b.status, r);
+    if (np > p.piece_cap) {
+        if (!kScatter) b.big[atomicAdd(&b.meta[kMetaBig], 1u)] = (uint32_t)t;
         np = 0;
     }
-    // lanes walk their pieces in lockstep so that neighbouring tets, which
-    // mostly share tiles, aggregate their increments
     const int32_t ny_ = r.y1 - r.y0 + 1, nz_ = r.z1 - r.z0 + 1;
-    int32_t maxp = np;
-    for (int off = 32; off > 0; off >>= 1) maxp = max(maxp, __shfl_xor(maxp, off));
-    for (int32_t k = 0; k < maxp; ++k) {
-        const bool act = k < np;
-        uint32_t key = 0;
-        if (act) {
-            const int32_t dz = k % nz_, rest = k / nz_;
-            const int32_t dy = rest % ny_, dx = rest / ny_;
-            key = tile_id(r.x0 + dx, r.y0 + dy, r.z0 + dz, p);
-        }
-        aggregated_inc(b.tile_count, key, act);
+    for (int32_t k = 0; k < np; ++k) {
+        const int32_t dz = k % nz_, rest = k / nz_;
+        const int32_t dy = rest % ny_, dx = rest / ny_;
+        const uint32_t key = tile_id(r.x0 + dx, r.y0 + dy, r.z0 + dz, p);
+        const uint32_t h = hash_insert(s_key, key);
+        const uint32_t rank = atomicAdd(s_cnt + h, 1u);
+        s_ref[tid * kPieceCapMax + k] = (h << 16) | rank;
+    }
+    __syncthreads();
+    for (int i = tid; i < kHashSlots; i += kBinThreads) {
+        const uint32_t key = s_key[i];
+        if (key == kEmptyKey) continue;
+        if (kScatter) s_cnt[i] = b.tile_off[key] + atomicAdd(b.tile_cursor + key, s_cnt[i]);
+        else atomicAdd(b.tile_count + key, s_cnt[i]);
+    }
+    if (!kScatter) return;
+    __syncthreads();
+    for (int32_t k = 0; k < np; ++k) {
+        const uint32_t ref = s_ref[tid * kPieceCapMax + k];
+        b.pieces[s_cnt[ref >> 16] + (ref & 0xffffu)] = (uint32_t)t;
     }
 }
 
@@ -251,32 +267,6 @@ __global__ void __launch_bounds__(1024) k_scan_tiles(TilePlan p, BinBuffers b) {
     }
 }
 
-// Pass 2: write every piece's tet id into its tile's slot range.
-__global__ void k_bin_scatter(const int4 *__restrict__ q4, int64_t nv,
-                              const int4 *__restrict__ tets, int64_t nt, GridGeom g, TilePlan p,
-                              BinBuffers b) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    TileRange r = {0, -1, 0, -1, 0, -1};
-    int32_t np = 0;
-    // status flags were raised by the counting pass already
-    if (t < nt) np = tet_pieces(q4, nv, tets, t, g, p, nullptr, r);
-    if (np > p.piece_cap) np = 0;
-    const int32_t ny_ = r.y1 - r.y0 + 1, nz_ = r.z1 - r.z0 + 1;
-    int32_t maxp = np;
-    for (int off = 32; off > 0; off >>= 1) maxp = max(maxp, __shfl_xor(maxp, off));
-    for (int32_t k = 0; k < maxp; ++k) {
-        const bool act = k < np;
-        uint32_t key = 0;
-        if (act) {
-            const int32_t dz = k % nz_, rest = k / nz_;
-            const int32_t dy = rest % ny_, dx = rest / ny_;
-            key = tile_id(r.x0 + dx, r.y0 + dy, r.z0 + dz, p);
-        }
-        const uint32_t rank = aggregated_inc(b.tile_cursor, key, act);
-        if (act) b.pieces[b.tile_off[key] + rank] = (uint32_t)t;
-    }
-}
-
 // Global word index of word w of tile-local column cl in tile `tile`.
 __device__ __forceinline__ int64_t tile_word(uint32_t tile, int32_t cl, int32_t w,
                                              const GridGeom &g, const TilePlan &p) {
@@ -302,15 +292,17 @@ __global__ void k_zero_shared_tiles(GridGeom g, TilePlan p, BinBuffers b, uint32
 // ------------------------------------------------------ tile voxelization
 
 constexpr int kTileThreads = 256;
-constexpr int kMaxTileWords = 8192;  // 32 KiB of LDS bitmap
+constexpr int kMaxTileWords = 4096;  // 16 KiB of LDS bitmap
+constexpr int kRowPool = 4096;       // per-batch row entries (16 KiB)
 
 struct PieceRec {
     Face f[4];
-    int16_t ci0, cj0;  // tile-local column origin of the clipped box
-    int16_t ni, nj;    // clipped box extent in columns
-    int16_t k0, nk;    // tile-local first z index and z extent
-    uint16_t lower;    // faces that start the span
-    uint16_t ncols;    // ni * nj (<= 1024)
+    int16_t ci0, cj0;   // tile-local column origin of the clipped box
+    int16_t ni, k0;     // rows (x extent) of the clipped box; tile-local first z index
+    int16_t nk;         // z extent
+    uint16_t lower;     // faces that start the span
+    uint16_t row0;      // first entry of this piece's rows in the row pool
+    uint16_t ncols;     // columns kept after culling (<= 1024)
 };
 
 // z span [lo, hi) (box-relative) of column (di, dj) of a piece.
@@ -321,11 +313,44 @@ __device__ __forceinline__ void column_span(const Face f[4], uint32_t lower, dou
 #pragma unroll
     for (int fi = 0; fi < 4; ++fi) {
         const double a = fma(f[fi].SY, dj, fma(f[fi].SX, di, f[fi].A));
-        const int32_t t = face_threshold(f[fi], a, nk, nkd);
+        const int32_t t = face_threshold(f[fi], a, nkd);
         const bool isl = (lower >> fi) & 1u;
         lo = isl ? max(lo, t) : lo;
         hi = isl ? hi : min(hi, t);
     }
+}
+
+// Columns of row x = cx (lattice) that the tet's projection onto the xy
+// plane can reach: the cross-section of the tet's vertex hull with the plane
+// x = cx spans y in [ylo, yhi], the extremes over the 6 vertex pairs whose
+// segment meets the plane.  Evaluated in double with a one-unit margin on
+// each side (conservative); the exact span test decides every column kept.
+// Returns the inclusive index range [j0, j1] (empty when j0 > j1).
+__device__ __forceinline__ void row_columns(const double vx[4], const double vy[4], double cx,
+                                            const GridGeom &g, int32_t &j0, int32_t &j1) {
+    double ylo = 1e300, yhi = -1e300;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+#pragma unroll
+        for (int c = a + 1; c < 4; ++c) {
+            const double da = vx[a] - cx, dc = vx[c] - cx;
+            if (da * dc <= 0.0) {  // the segment meets the plane (or lies in it)
+                double y;
+                if (vx[a] == vx[c]) {
+                    ylo = fmin(ylo, fmin(vy[a], vy[c]));
+                    yhi = fmax(yhi, fmax(vy[a], vy[c]));
+                } else {
+                    y = vy[a] + (vy[c] - vy[a]) * (da / (vx[a] - vx[c]));
+                    ylo = fmin(ylo, y);
+                    yhi = fmax(yhi, y);
+                }
+            }
+        }
+    }
+    // centers (2j+1)S with ylo - 1 <= (2j+1)S <= yhi + 1
+    const double S = (double)g.half[1], inv = 1.0 / (2.0 * S);
+    j0 = (int32_t)ceil((ylo - 1.0 - S) * inv);
+    j1 = (int32_t)floor((yhi + 1.0 - S) * inv);
 }
 
 __global__ void __launch_bounds__(kTileThreads)
@@ -333,14 +358,16 @@ __global__ void __launch_bounds__(kTileThreads)
                     TilePlan p, BinBuffers b, uint32_t *__restrict__ grid, int strict) {
     __shared__ uint32_t s_bits[kMaxTileWords];
     __shared__ PieceRec s_rec[kTileThreads];
+    __shared__ uint32_t s_row[kRowPool];  // j0 (8 bits) | count (8 bits) | prefix (16 bits)
     __shared__ uint32_t s_soff[kTileThreads + 1];
-    __shared__ uint32_t s_chunk, s_tile, s_p0, s_p1, s_shared;
+    __shared__ uint32_t s_roff[kTileThreads + 1];
+    __shared__ uint32_t s_chunk, s_tile, s_p0, s_p1, s_shared, s_nb;
 
     const int tid = threadIdx.x;
     const int32_t tw = 1 << p.lw;
     const int32_t tcols = 1 << (p.lx + p.ly);
     const int32_t nwords = tcols * tw;
-    const int32_t strip = p.strip;
+    const uint32_t strip = (uint32_t)p.strip;
     const uint32_t total = b.meta[kMetaChunks];
 
     for (;;) {
@@ -349,7 +376,7 @@ __global__ void __launch_bounds__(kTileThreads)
             s_chunk = c;
             if (c < total) {
                 // tile = last t with chunk_off[t] <= c
-                uint32_t lo = 0, hi = (uint32_t)p.ntiles;  // invariant chunk_off[lo] <= c < chunk_off[hi]
+                uint32_t lo = 0, hi = (uint32_t)p.ntiles;  // chunk_off[lo] <= c < chunk_off[hi]
                 while (hi - lo > 1) {
                     const uint32_t mid = (lo + hi) >> 1;
                     if (b.chunk_off[mid] <= c) lo = mid;
@@ -366,7 +393,7 @@ __global__ void __launch_bounds__(kTileThreads)
         }
         __syncthreads();
         if (s_chunk >= total) break;
-        const uint32_t tile = s_tile, p0 = s_p0, p1 = s_p1;
+        const uint32_t tile = s_tile, p1 = s_p1;
         for (int32_t x = tid; x < nwords; x += kTileThreads) s_bits[x] = 0u;
 
         // tile origin in voxel indices
@@ -377,15 +404,19 @@ __global__ void __launch_bounds__(kTileThreads)
         const int32_t ti1 = ti0 + (1 << p.lx) - 1, tj1 = tj0 + (1 << p.ly) - 1;
         const int32_t tk1 = min(tk0 + (tw << 5) - 1, g.n[2] - 1);
 
-        for (uint32_t pb = p0; pb < p1; pb += kTileThreads) {
-            // phase 1: one lane per piece -> record in LDS
-            uint32_t nstrips = 0;
+        uint32_t pb = s_p0;
+        while (pb < p1) {
+            // phase 1a: one lane per piece: clipped box, faces -> record
             const uint32_t pi = pb + tid;
+            int32_t lo[3] = {0, 0, 0}, hi[3] = {-1, -1, -1};
+            double vx[4], vy[4];
+            uint32_t nrows = 0;
             if (pi < p1) {
                 const uint32_t t = b.pieces[pi];
                 const int4 T = tets[t];
                 const int4 A = q4[T.x], B = q4[T.y], C = q4[T.z], D = q4[T.w];
-                int32_t lo[3], hi[3];
+                vx[0] = A.x; vx[1] = B.x; vx[2] = C.x; vx[3] = D.x;
+                vy[0] = A.y; vy[1] = B.y; vy[2] = C.y; vy[3] = D.y;
                 candidate_box(A, B, C, D, g, lo, hi);
                 lo[0] = max(lo[0], ti0);
                 hi[0] = min(hi[0], ti1);
@@ -393,7 +424,6 @@ __global__ void __launch_bounds__(kTileThreads)
                 hi[1] = min(hi[1], tj1);
                 lo[2] = max(lo[2], tk0);
                 hi[2] = min(hi[2], tk1);
-                PieceRec &R = s_rec[tid];
                 if (lo[0] <= hi[0] && lo[1] <= hi[1] && lo[2] <= hi[2]) {
                     const double p0d[3] = {(double)((2 * lo[0] + 1) * g.half[0]),
                                            (double)((2 * lo[1] + 1) * g.half[1]),
@@ -401,42 +431,89 @@ __global__ void __launch_bounds__(kTileThreads)
                     Face f[4];
                     uint32_t lower;
                     if (build_faces(A, B, C, D, p0d, g, strict != 0, f, lower)) {
+                        PieceRec &R = s_rec[tid];
 #pragma unroll
                         for (int fi = 0; fi < 4; ++fi) R.f[fi] = f[fi];
                         R.ci0 = (int16_t)(lo[0] - ti0);
                         R.cj0 = (int16_t)(lo[1] - tj0);
                         R.ni = (int16_t)(hi[0] - lo[0] + 1);
-                        R.nj = (int16_t)(hi[1] - lo[1] + 1);
                         R.k0 = (int16_t)(lo[2] - tk0);
                         R.nk = (int16_t)(hi[2] - lo[2] + 1);
                         R.lower = (uint16_t)lower;
-                        R.ncols = (uint16_t)(R.ni * R.nj);
-                        nstrips = ((uint32_t)R.ncols + strip - 1) / strip;
+                        nrows = (uint32_t)(hi[0] - lo[0] + 1);
                     }
                 }
             }
-            // phase 2: exclusive scan of strip counts (wave scan + wave sums)
-            s_soff[tid] = nstrips;
+            // phase 1b: row-pool offsets; the batch ends before the first
+            // piece whose rows no longer fit (a piece has at most 32 rows, so
+            // every batch makes progress)
+            s_roff[tid] = nrows;
             __syncthreads();
             if (tid < 64) {
-                // 4 waves x 64 lanes: each of the first 64 threads scans 4 entries
-                uint32_t v0 = s_soff[4 * tid], v1 = s_soff[4 * tid + 1], v2 = s_soff[4 * tid + 2],
-                         v3 = s_soff[4 * tid + 3];
+                const uint32_t v0 = s_roff[4 * tid], v1 = s_roff[4 * tid + 1],
+                               v2 = s_roff[4 * tid + 2], v3 = s_roff[4 * tid + 3];
                 const uint32_t sum = v0 + v1 + v2 + v3;
                 uint32_t incl = sum;
                 for (int off = 1; off < 64; off <<= 1) {
                     const uint32_t o = __shfl_up(incl, off);
                     if (tid >= off) incl += o;
                 }
-                const uint32_t excl = incl - sum;
-                s_soff[4 * tid] = excl;
-                s_soff[4 * tid + 1] = excl + v0;
-                s_soff[4 * tid + 2] = excl + v0 + v1;
-                s_soff[4 * tid + 3] = excl + v0 + v1 + v2;
+                const uint32_t ex = incl - sum;
+                const uint32_t e[4] = {ex, ex + v0, ex + v0 + v1, ex + v0 + v1 + v2};
+                const uint32_t v[4] = {v0, v1, v2, v3};
+                uint32_t first_over = kTileThreads;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    s_roff[4 * tid + q] = e[q];
+                    if (e[q] + v[q] > (uint32_t)kRowPool) first_over = min(first_over, (uint32_t)(4 * tid + q));
+                }
+                for (int off = 32; off > 0; off >>= 1) first_over = min(first_over, (uint32_t)__shfl_xor((int)first_over, off));
+                if (tid == 0) s_nb = min(first_over, p1 - pb);
+            }
+            __syncthreads();
+            const uint32_t nb = s_nb;
+            // phase 1c: per-row column ranges of the pieces in this batch
+            uint32_t nstrips = 0;
+            if ((uint32_t)tid < nb && nrows) {
+                PieceRec &R = s_rec[tid];
+                const uint32_t base = s_roff[tid];
+                uint32_t prefix = 0;
+                for (uint32_t rr = 0; rr < nrows; ++rr) {
+                    const double cx = (double)((2 * (lo[0] + (int32_t)rr) + 1) * g.half[0]);
+                    int32_t j0, j1;
+                    row_columns(vx, vy, cx, g, j0, j1);
+                    j0 = max(j0, lo[1]);
+                    j1 = min(j1, hi[1]);
+                    const uint32_t cnt = j1 >= j0 ? (uint32_t)(j1 - j0 + 1) : 0u;
+                    const uint32_t jrel = j1 >= j0 ? (uint32_t)(j0 - lo[1]) : 0u;
+                    s_row[base + rr] = jrel | (cnt << 8) | (prefix << 16);
+                    prefix += cnt;
+                }
+                R.row0 = (uint16_t)base;
+                R.ncols = (uint16_t)prefix;
+                nstrips = (prefix + strip - 1) / strip;
+            }
+            // phase 2: exclusive scan of strip counts
+            s_soff[tid] = nstrips;
+            __syncthreads();
+            if (tid < 64) {
+                const uint32_t v0 = s_soff[4 * tid], v1 = s_soff[4 * tid + 1],
+                               v2 = s_soff[4 * tid + 2], v3 = s_soff[4 * tid + 3];
+                const uint32_t sum = v0 + v1 + v2 + v3;
+                uint32_t incl = sum;
+                for (int off = 1; off < 64; off <<= 1) {
+                    const uint32_t o = __shfl_up(incl, off);
+                    if (tid >= off) incl += o;
+                }
+                const uint32_t ex = incl - sum;
+                s_soff[4 * tid] = ex;
+                s_soff[4 * tid + 1] = ex + v0;
+                s_soff[4 * tid + 2] = ex + v0 + v1;
+                s_soff[4 * tid + 3] = ex + v0 + v1 + v2;
                 if (tid == 63) s_soff[kTileThreads] = incl;
             }
             __syncthreads();
-            // phase 3: strips of `strip` columns, one per lane
+            // phase 3: strips of `strip` kept columns, one per lane
             const uint32_t nst = s_soff[kTileThreads];
             for (uint32_t s = tid; s < nst; s += kTileThreads) {
                 int32_t lo_r = 0, hi_r = kTileThreads;  // s_soff[lo_r] <= s < s_soff[hi_r]
@@ -450,24 +527,41 @@ __global__ void __launch_bounds__(kTileThreads)
 #pragma unroll
                 for (int fi = 0; fi < 4; ++fi) f[fi] = R.f[fi];
                 const uint32_t lower = R.lower;
-                const int32_t nj = R.nj, nk = R.nk, k0 = R.k0, ci0 = R.ci0, cj0 = R.cj0;
+                const int32_t nk = R.nk, k0 = R.k0, ci0 = R.ci0, cj0 = R.cj0;
+                const uint32_t row0 = R.row0, ni = (uint32_t)R.ni;
                 const double nkd = (double)nk;
-                const uint32_t c0 = (s - s_soff[lo_r]) * (uint32_t)strip;
-                const uint32_t c1 = min(c0 + (uint32_t)strip, (uint32_t)R.ncols);
-                int32_t di = (int32_t)(c0 / (uint32_t)nj);
-                int32_t dj = (int32_t)(c0 - (uint32_t)di * (uint32_t)nj);
+                const uint32_t c0 = (s - s_soff[lo_r]) * strip;
+                const uint32_t c1 = min(c0 + strip, (uint32_t)R.ncols);
+                // row holding kept column c0: last row with prefix <= c0
+                uint32_t ra = 0, rb = ni;
+                while (rb - ra > 1) {
+                    const uint32_t mid = (ra + rb) >> 1;
+                    if ((s_row[row0 + mid] >> 16) <= c0) ra = mid;
+                    else rb = mid;
+                }
+                uint32_t rw = s_row[row0 + ra];
+                int32_t di = (int32_t)ra;
+                int32_t dj = (int32_t)(rw & 0xffu) + (int32_t)(c0 - (rw >> 16));
+                int32_t jend = (int32_t)(rw & 0xffu) + (int32_t)((rw >> 8) & 0xffu);
                 for (uint32_t c = c0; c < c1; ++c) {
-                    int32_t lo, hi;
-                    column_span(f, lower, (double)di, (double)dj, nk, nkd, lo, hi);
-                    if (lo < hi)
-                        or_run_lds(s_bits + (((ci0 + di) << p.ly) + cj0 + dj) * tw, k0 + lo, k0 + hi);
-                    if (++dj == nj) {
-                        dj = 0;
-                        ++di;
+                    int32_t zlo, zhi;
+                    column_span(f, lower, (double)di, (double)dj, nk, nkd, zlo, zhi);
+                    if (zlo < zhi)
+                        or_run_lds(s_bits + (((ci0 + di) << p.ly) + cj0 + dj) * tw, k0 + zlo,
+                                   k0 + zhi);
+                    if (++dj == jend && c + 1 < c1) {
+                        // next row with kept columns
+                        do {
+                            ++di;
+                            rw = s_row[row0 + di];
+                        } while (((rw >> 8) & 0xffu) == 0u);
+                        dj = (int32_t)(rw & 0xffu);
+                        jend = dj + (int32_t)((rw >> 8) & 0xffu);
                     }
                 }
             }
             __syncthreads();
+            pb += nb;
         }
 
         // flush the tile: word x of the bitmap is word (x & (tw-1)) of
@@ -589,7 +683,9 @@ void launch_clear(uint32_t *p, int64_t nwords, hipStream_t s) {
 
 void launch_bin_count(const int4 *q4, int64_t nv, const int4 *tets, int64_t nt, const GridGeom &g,
                       const TilePlan &p, const BinBuffers &b, hipStream_t s) {
-    if (nt > 0) k_bin_count<<<blocks_for(nt), kBlock, 0, s>>>(q4, nv, tets, nt, g, p, b);
+    if (nt > 0)
+        k_bin<false><<<(unsigned)((nt + kBinThreads - 1) / kBinThreads), kBinThreads, 0, s>>>(
+            q4, nv, tets, nt, g, p, b);
 }
 
 void launch_scan_tiles(const TilePlan &p, const BinBuffers &b, hipStream_t s) {
@@ -598,7 +694,9 @@ void launch_scan_tiles(const TilePlan &p, const BinBuffers &b, hipStream_t s) {
 
 void launch_bin_scatter(const int4 *q4, int64_t nv, const int4 *tets, int64_t nt,
                         const GridGeom &g, const TilePlan &p, const BinBuffers &b, hipStream_t s) {
-    if (nt > 0) k_bin_scatter<<<blocks_for(nt), kBlock, 0, s>>>(q4, nv, tets, nt, g, p, b);
+    if (nt > 0)
+        k_bin<true><<<(unsigned)((nt + kBinThreads - 1) / kBinThreads), kBinThreads, 0, s>>>(
+            q4, nv, tets, nt, g, p, b);
 }
 
 void launch_zero_shared_tiles(const GridGeom &g, const TilePlan &p, const BinBuffers &b,

@@ -25,13 +25,13 @@ inline int ilog2(int64_t n) {
     return s;
 }
 
-// Tiles of at most 32 x 32 columns x 8 words (32 KiB of LDS bitmap), made
+// Tiles of at most 32 x 32 columns x 4 words (16 KiB of LDS bitmap), made
 // smaller (down to 8 x 8 columns) while the grid has fewer than
 // `min_tiles` of them, so that small grids still spread over the chip.
 inline TilePlan plan_tiles(tv_dims d, int64_t min_tiles) {
     TilePlan p;
     const int W = (d.nz + 31) / 32;
-    p.lw = ilog2(W) < 3 ? ilog2(W) : 3;
+    p.lw = ilog2(W) < 2 ? ilog2(W) : 2;
     p.lx = ilog2(d.nx) < 5 ? ilog2(d.nx) : 5;
     p.ly = ilog2(d.ny) < 5 ? ilog2(d.ny) : 5;
     auto count = [&]() {
