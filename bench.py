@@ -14,6 +14,9 @@ Workloads (seeded synthetic Kuhn meshes, see paper_2106_01326_amd/synth.py):
   large   128^3 cubes x 6 tets, jitter 0.45, 6 ellipsoids, 1024^3 grid, fp32 (default)
   medium  64^3 cubes x 6 tets, jitter 0.3, 3 ellipsoids, 256^3 grid, int32 lattice verts
   small   8^3 cubes x 6 tets, jitter 0.2, sphere, 32^3 grid, fp32
+  batch   1024 meshes of uneven size (cubes per axis U{4..48}, jitter U[0,0.4],
+          1-4 ellipsoids, 32^3 or 64^3 grids): one batched call vs the
+          per-mesh loop, meshes/s and tets/s
 """
 from __future__ import annotations
 
@@ -125,12 +128,110 @@ def cpu_baseline(m, gpu_words_fn, target_s=12.0):
             "seconds": dt, "gpu_bit_exact_on_sample": exact}
 
 
+def bench_batch(args, torch, tv):
+    """Batched voxelization of the uneven batch vs a loop of single-mesh
+    calls (the per-mesh baseline: back to back on one stream, one final
+    sync -- its best case)."""
+    from paper_2106_01326_amd import synth
+
+    log(f"generating {args.batch_meshes} meshes")
+    t0 = time.perf_counter()
+    meshes = synth.workload_batch(count=args.batch_meshes)
+    nt = sum(m.nt for m in meshes)
+    log(f"generated {len(meshes)} meshes, {nt} tets in {time.perf_counter() - t0:.1f} s")
+    dev = torch.device("cuda:0")
+    items = [(torch.from_numpy(m.verts).to(dev), torch.from_numpy(m.tets).to(dev), m.dims, m.bbox, False)
+             for m in meshes]
+    stream = torch.cuda.current_stream()
+    batch = tv.Batch(items)
+    for _ in range(args.warmup):
+        batch.run(stream=stream)
+    torch.cuda.synchronize()
+    tv.profile_read()
+    tv.profile_enable(True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        batch.run(stream=stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    tv.profile_enable(False)
+    stages, calls = tv.profile_read()
+    ms_batch = ev0.elapsed_time(ev1) / args.steps
+    bad = [i for i in range(len(meshes)) if batch.status(i) != tv.TV_OK]
+    assert not bad, f"status errors in meshes {bad[:5]}"
+    log(f"batched: {ms_batch:.3f} ms per batch; stages {stages}")
+
+    # per-mesh loop with preallocated grids and workspaces
+    grids = [tv.alloc_grid(m.dims, dev) for m in meshes]
+    wss = [tv.alloc_workspace(tv.workspace_bytes(m.nv, m.nt, m.dims), dev) for m in meshes]
+
+    def loop():
+        for (v, t, dims, bbox, _), g, w in zip(items, grids, wss):
+            tv.voxelize(v, t, dims, bbox, grid=g, workspace=w, stream=stream)
+
+    loop()
+    torch.cuda.synchronize()
+    reps = max(1, min(3, args.steps))
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(reps):
+        loop()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_loop = ev0.elapsed_time(ev1) / reps
+    wall_loop = (time.perf_counter() - t0) * 1e3 / reps
+    same = all(torch.equal(a, b) for a, b in zip(grids, batch.grids))
+    log(f"per-mesh loop: {ms_loop:.3f} ms per pass (host wall {wall_loop:.3f} ms); identical={same}")
+
+    out = {"metric": "meshes/s (batched)", "value": len(meshes) / (ms_batch * 1e-3), "unit": "meshes/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_batch,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic (seeded jittered Kuhn meshes)",
+           "config": {"workload": "uneven batch (config 3)", "meshes": len(meshes), "tets": nt,
+                      "grids": "32^3 or 64^3", "vert_format": "f32"},
+           "tets_per_s": nt / (ms_batch * 1e-3),
+           "per_mesh_loop": {"meshes_per_s": len(meshes) / (ms_loop * 1e-3), "ms_per_pass": ms_loop,
+                             "host_wall_ms_per_pass": wall_loop},
+           "batched_over_per_mesh": ms_loop / ms_batch, "bit_identical_to_per_mesh": bool(same),
+           "stage_ms": {k: v_ / max(calls, 1) for k, v_ in stages.items()}}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_batch(meshes, batch, args.cpu_seconds)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_batch(meshes, batch, target_s):
+    """The oracle on the first meshes of the batch until about target_s of
+    wall time; compared bit for bit with the batched GPU grids."""
+    import oracle
+
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    cores = max(1, min(cores, 16))
+    t0 = time.perf_counter()
+    n = 0
+    tets = 0
+    exact = True
+    while n < len(meshes) and time.perf_counter() - t0 < target_s:
+        m = meshes[n]
+        w = oracle.voxelize_mesh(m, threads=cores)
+        exact = exact and bool(np.array_equal(w, batch.grids[n].cpu().numpy().view(np.uint32)))
+        tets += m.nt
+        n += 1
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "meshes/s", "tets_per_s": tets / dt, "cores": cores, "kind": "oracle",
+            "sample": f"first {n} of {len(meshes)} meshes ({tets} tets, {dt:.1f} s wall incl. GPU readback)",
+            "gpu_bit_exact_on_sample": exact}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="large", choices=["large", "medium", "small"])
+    ap.add_argument("--workload", default="large", choices=["large", "medium", "small", "batch"])
+    ap.add_argument("--batch-meshes", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     args = ap.parse_args()
@@ -147,6 +248,8 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("no GPU visible")
     tv.load_library()
+    if args.workload == "batch":
+        return bench_batch(args, torch, tv)
     log(f"generating workload {args.workload}")
     t0 = time.perf_counter()
     m = make_workload(args.workload)

@@ -111,6 +111,36 @@ tv_status tv_voxelize_q(const int32_t *qverts, int64_t nv, const int32_t *tets, 
                         uint32_t flags);
 
 /*
+ * Batches: many meshes of uneven size voxelized by one launch sequence
+ * (each mesh into its own grid).  `meshes` is a HOST array of n descriptors
+ * whose pointers are device pointers; vert_format selects fp32 world
+ * coordinates (snapped with the mesh's bbox) or int32 lattice coordinates.
+ * Results equal the meshes' single-mesh results bit for bit.  Per-mesh data
+ * errors land in status word i (tv_fetch_status(ws, i, stream)) and never
+ * affect another mesh.  Host-side argument errors name the offending mesh
+ * in tv_last_error() and enqueue nothing.  The descriptor table is copied
+ * into the workspace during the call (from pageable host memory; the host
+ * array may be reused when the call returns).
+ */
+#define TV_VERTS_F32 0u
+#define TV_VERTS_Q32 1u
+
+typedef struct {
+    const void *verts;    /* device [nv][3]: float32 world or int32 lattice */
+    uint32_t vert_format; /* TV_VERTS_F32 or TV_VERTS_Q32 */
+    int64_t nv;
+    const int32_t *tets;  /* device [nt][4] int32, 16-byte aligned */
+    int64_t nt;
+    tv_dims dims;
+    tv_bbox bbox;         /* used with TV_VERTS_F32 */
+    uint32_t *grid;       /* device, tv_grid_words(dims) words, written entirely */
+} tv_mesh;
+
+size_t tv_batch_workspace_bytes(const tv_mesh *meshes, int32_t n, uint32_t flags);
+tv_status tv_voxelize_batch(const tv_mesh *meshes, int32_t n, void *ws, size_t ws_bytes,
+                            void *stream, uint32_t flags);
+
+/*
  * Snap only: fp32 world coordinates verts [nv][3] -> lattice coordinates
  * q_out [nv][3] int32 (both device), per the snap rule above.  A vertex that
  * is NaN or off the lattice range is written as three TV_Q_INVALID values.
@@ -121,9 +151,10 @@ tv_status tv_snap(const float *verts, int64_t nv, tv_bbox bbox, int32_t *q_out, 
 
 /*
  * Data-error status of mesh `mesh_index` recorded in workspace `ws` by the
- * last call that used it (index 0 for the single-mesh calls).  Synchronizes
- * `stream`, then returns TV_OK, TV_ERR_INDEX or TV_ERR_RANGE (TV_ERR_INDEX
- * wins when both occurred), or TV_ERR_INVALID_ARG / TV_ERR_HIP.
+ * last call that used it (index 0 for the single-mesh calls, the mesh's
+ * position for a batch).  Synchronizes `stream`, then returns TV_OK,
+ * TV_ERR_INDEX or TV_ERR_RANGE (TV_ERR_INDEX wins when both occurred), or
+ * TV_ERR_INVALID_ARG (index outside the last call's meshes) / TV_ERR_HIP.
  */
 tv_status tv_fetch_status(const void *ws, int32_t mesh_index, void *stream);
 

@@ -31,7 +31,11 @@ TIE_STRICT = 1
 PATH_PER_TET = 2
 Q_INVALID = -(1 << 31)
 
+VERTS_F32 = 0
+VERTS_Q32 = 1
+
 EXPORTED = ("tv_grid_words", "tv_workspace_bytes", "tv_voxelize", "tv_voxelize_q", "tv_snap",
+            "tv_batch_workspace_bytes", "tv_voxelize_batch",
             "tv_fetch_status", "tv_status_string", "tv_last_error", "tv_profile_enable",
             "tv_profile_read", "tv_profile_stage_name")
 
@@ -42,6 +46,12 @@ class Dims(ctypes.Structure):
 
 class BBox(ctypes.Structure):
     _fields_ = [("lo", ctypes.c_float * 3), ("hi", ctypes.c_float * 3)]
+
+
+class MeshC(ctypes.Structure):
+    _fields_ = [("verts", ctypes.c_void_p), ("vert_format", ctypes.c_uint32), ("nv", ctypes.c_int64),
+                ("tets", ctypes.c_void_p), ("nt", ctypes.c_int64), ("dims", Dims), ("bbox", BBox),
+                ("grid", ctypes.c_void_p)]
 
 
 class TVError(RuntimeError):
@@ -78,6 +88,10 @@ def load_library():
     lib.tv_voxelize.restype = st
     lib.tv_voxelize_q.argtypes = [P, i64, P, i64, Dims, P, P, ctypes.c_size_t, P, u32]
     lib.tv_voxelize_q.restype = st
+    lib.tv_batch_workspace_bytes.argtypes = [P, ctypes.c_int32, u32]
+    lib.tv_batch_workspace_bytes.restype = ctypes.c_size_t
+    lib.tv_voxelize_batch.argtypes = [P, ctypes.c_int32, P, ctypes.c_size_t, P, u32]
+    lib.tv_voxelize_batch.restype = st
     lib.tv_snap.argtypes = [P, i64, BBox, P, P]
     lib.tv_snap.restype = st
     lib.tv_fetch_status.argtypes = [P, ctypes.c_int32, P]
@@ -237,3 +251,56 @@ def profile_read() -> tuple[dict, int]:
                                ctypes.cast(ctypes.pointer(calls), ctypes.c_void_p)))
     out = {lib.tv_profile_stage_name(i).decode(): ms[i] for i in range(n.value)}
     return out, int(calls.value)
+
+
+def _mesh_struct(verts, tets, dims, bbox, grid, qverts):
+    torch = _torch()
+    vptr, nv = _dev_ptr(verts, torch.int32 if qverts else torch.float32, 3, "verts")
+    tptr, nt = _dev_ptr(tets, torch.int32, 4, "tets")
+    gptr, _ = _dev_ptr(grid, torch.int32, None, "grid")
+    if grid.numel() < grid_words(dims):
+        raise ValueError("grid tensor too small")
+    if bbox is None:
+        bbox = ((0.0, 0.0, 0.0), (1.0, 1.0, 1.0))
+    return MeshC(vptr.value, VERTS_Q32 if qverts else VERTS_F32, nv, tptr.value, nt, _dims(dims),
+                 _bbox(bbox), gptr.value)
+
+
+class Batch:
+    """A prepared batch: device tensors of many meshes and their descriptor
+    array, reusable across calls (the grids are overwritten each call)."""
+
+    def __init__(self, items, device=None):
+        """items: iterable of (verts, tets, dims, bbox, qverts) with device
+        tensors; a grid is allocated per mesh."""
+        torch = _torch()
+        self.items = list(items)
+        self.grids = [alloc_grid(it[2], it[0].device) for it in self.items]
+        n = len(self.items)
+        self.array = (MeshC * n)()
+        for i, ((v, t, dims, bbox, q), g) in enumerate(zip(self.items, self.grids)):
+            self.array[i] = _mesh_struct(v, t, dims, bbox, g, q)
+        self.n = n
+        need = int(load_library().tv_batch_workspace_bytes(ctypes.cast(self.array, ctypes.c_void_p), n, 0))
+        if need == 0:
+            _check(TV_ERR_INVALID_ARG)
+        self.workspace = alloc_workspace(need, self.items[0][0].device if n else device)
+        del torch
+
+    def run(self, strict=False, per_tet=False, stream=None):
+        flags = (TIE_STRICT if strict else TIE_HALF_OPEN) | (PATH_PER_TET if per_tet else 0)
+        lib = load_library()
+        _check(lib.tv_voxelize_batch(ctypes.cast(self.array, ctypes.c_void_p), self.n,
+                                     ctypes.c_void_p(self.workspace.data_ptr()), self.workspace.numel(),
+                                     _stream_handle(stream), flags))
+        return self.grids
+
+    def status(self, i, stream=None):
+        return fetch_status(self.workspace, i, stream)
+
+
+def voxelize_batch(items, strict=False, per_tet=False, stream=None):
+    """Voxelize many meshes in one launch sequence.  items: list of
+    (verts, tets, dims, bbox, qverts).  Returns (grids, Batch)."""
+    b = Batch(items)
+    return b.run(strict=strict, per_tet=per_tet, stream=stream), b

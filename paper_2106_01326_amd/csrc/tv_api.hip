@@ -1,11 +1,13 @@
 // C ABI of the voxelizer: argument checks, workspace carving and the launch
-// sequence of the single-mesh path.  Declarations and the contract are in
-// include/tv.h.
+// sequence shared by the single-mesh and batch calls.  Declarations and the
+// contract are in include/tv.h.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
+
+#include <vector>
 
 #include "tv.h"
 #include "tv_kernels.h"
@@ -16,9 +18,10 @@ namespace {
 
 thread_local char g_last_error[256] = "";
 
-// Tiles wanted per grid before tiles are made smaller (independent of the
-// device so that workspace sizes do not depend on it).
-constexpr int64_t kMinTiles = 512;
+// Tiles wanted per lone grid before tiles are made smaller (independent of
+// the device so that workspace sizes do not depend on it).
+constexpr int64_t kMinTilesSingle = 512;
+constexpr int64_t kMinTilesBatch = 1;
 
 tv_status fail(tv_status code, const char *fmt, ...) {
     va_list ap;
@@ -66,99 +69,183 @@ int device_cus() {
 constexpr uint32_t kKnownFlags = TV_TIE_STRICT | TV_PATH_PER_TET;
 constexpr int64_t kMaxTets = (int64_t)1 << 28;  // piece slots stay below 2^32
 
-tv_status check_common(int64_t nv, const int32_t *tets, int64_t nt, tv_dims dims, uint32_t *grid,
-                       void *ws, size_t ws_bytes, uint32_t flags, const void *verts) {
+// Host-visible checks of one mesh; `which` prefixes messages of batch entries.
+tv_status check_mesh(const void *verts, uint32_t fmt, int64_t nv, const int32_t *tets, int64_t nt,
+                     tv_dims dims, const tv_bbox *bbox, const uint32_t *grid, const char *which) {
     if (!pow2_dim(dims.nx) || !pow2_dim(dims.ny) || !pow2_dim(dims.nz))
         return fail(TV_ERR_UNSUPPORTED_DIMS,
-                    "dims (%d,%d,%d): each must be a power of two in [1,32768]", dims.nx, dims.ny,
-                    dims.nz);
+                    "%sdims (%d,%d,%d): each must be a power of two in [1,32768]", which, dims.nx,
+                    dims.ny, dims.nz);
     if (nv < 0 || nt < 0 || nv > INT32_MAX || nt > kMaxTets)
-        return fail(TV_ERR_INVALID_ARG, "sizes nv=%lld nt=%lld out of range", (long long)nv,
-                    (long long)nt);
-    if (!grid) return fail(TV_ERR_INVALID_ARG, "grid is null");
+        return fail(TV_ERR_INVALID_ARG, "%ssizes nv=%lld nt=%lld out of range", which,
+                    (long long)nv, (long long)nt);
+    if (!grid) return fail(TV_ERR_INVALID_ARG, "%sgrid is null", which);
     if (nt > 0 && (!tets || !verts || nv == 0))
-        return fail(TV_ERR_INVALID_ARG, "null vertex/tet array with nt > 0");
-    if (((uintptr_t)tets & 15u) || ((uintptr_t)verts & 3u))
-        return fail(TV_ERR_INVALID_ARG, "tets must be 16-byte and verts 4-byte aligned");
+        return fail(TV_ERR_INVALID_ARG, "%snull vertex/tet array with nt > 0", which);
+    if (((uintptr_t)tets & 15u) || ((uintptr_t)verts & 3u) || ((uintptr_t)grid & 3u))
+        return fail(TV_ERR_INVALID_ARG, "%stets must be 16-byte, verts and grid 4-byte aligned",
+                    which);
+    if (fmt != TV_VERTS_F32 && fmt != TV_VERTS_Q32)
+        return fail(TV_ERR_INVALID_ARG, "%sunknown vertex format %u", which, fmt);
+    if (fmt == TV_VERTS_F32) {
+        for (int a = 0; a < 3; ++a)
+            if (!isfinite(bbox->lo[a]) || !isfinite(bbox->hi[a]) || !(bbox->hi[a] > bbox->lo[a]))
+                return fail(TV_ERR_INVALID_ARG, "%sbbox axis %d: need finite lo < hi", which, a);
+    }
+    return TV_OK;
+}
+
+tv::MeshDesc make_desc(const void *verts, uint32_t fmt, int64_t nv, const int32_t *tets,
+                       int64_t nt, tv_dims dims, const tv_bbox *bbox, uint32_t *grid,
+                       int64_t min_tiles) {
+    tv::MeshDesc d;
+    memset(&d, 0, sizeof d);
+    d.verts = verts;
+    d.tets = reinterpret_cast<const int4 *>(tets);
+    d.grid = grid;
+    d.nv = nv;
+    d.nt = nt;
+    d.g = make_geom(dims);
+    d.p = tv::plan_tiles(dims, min_tiles);
+    d.fmt = fmt == TV_VERTS_F32 ? tv::kFmtF32 : tv::kFmtQ32;
+    if (fmt == TV_VERTS_F32) {
+        for (int a = 0; a < 3; ++a) {
+            d.box.lo[a] = (double)bbox->lo[a];
+            d.box.ext[a] = (double)bbox->hi[a] - (double)bbox->lo[a];
+        }
+    }
+    return d;
+}
+
+// Fills the bases of the descriptors and the call totals.
+tv::CallSizes assign_bases(std::vector<tv::MeshDesc> &descs) {
+    tv::CallSizes c = {(int64_t)descs.size(), 0, 0, 0};
+    for (size_t i = 0; i < descs.size(); ++i) {
+        tv::MeshDesc &d = descs[i];
+        d.mesh = (int32_t)i;
+        d.vert_base = c.nv;
+        d.tet_base = c.nt;
+        d.tile_base = c.ntiles;
+        c.nv += d.nv;
+        c.nt += d.nt;
+        c.ntiles += d.p.ntiles;
+    }
+    return c;
+}
+
+// The launch sequence of a call whose descriptors are final.
+tv_status run(std::vector<tv::MeshDesc> &descs, const tv::CallSizes &c, uint8_t *ws, hipStream_t s,
+              uint32_t flags) {
+    const tv::WorkspaceLayout L = tv::layout(c);
+    const tv::BinBuffers b = tv::bin_buffers(ws, L);
+    const bool strict = (flags & TV_TIE_STRICT) != 0;
+    tv::MeshTable T;
+    memset(&T, 0, sizeof T);
+    T.n = (int32_t)c.meshes;
+    T.chunk = tv::kChunkPieces;
+    T.strip = tv::kStripColumns;
+    T.piece_cap = tv::kPieceCap;
+    T.nv_total = c.nv;
+    T.nt_total = c.nt;
+    T.ntiles_total = c.ntiles;
+    if (c.meshes == 1) {
+        T.one = descs[0];
+    } else {
+        // descriptor table + prefix sums, copied into the workspace
+        std::vector<uint8_t> host(L.descs_bytes);
+        memcpy(host.data(), descs.data(), sizeof(tv::MeshDesc) * descs.size());
+        int64_t *pre = reinterpret_cast<int64_t *>(host.data() + sizeof(tv::MeshDesc) * descs.size());
+        const size_t n = descs.size();
+        for (size_t i = 0; i <= n; ++i) {
+            pre[i] = i < n ? descs[i].vert_base : c.nv;
+            pre[n + 1 + i] = i < n ? descs[i].tet_base : c.nt;
+            pre[2 * (n + 1) + i] = i < n ? descs[i].tile_base : c.ntiles;
+        }
+        uint8_t *dev = ws + L.descs;
+        if (hipMemcpyAsync(dev, host.data(), L.descs_bytes, hipMemcpyHostToDevice, s) != hipSuccess)
+            return fail(TV_ERR_HIP, "descriptor upload failed");
+        T.descs = reinterpret_cast<const tv::MeshDesc *>(dev);
+        const int64_t *dpre = reinterpret_cast<const int64_t *>(dev + sizeof(tv::MeshDesc) * n);
+        T.vert_pre = dpre;
+        T.tet_pre = dpre + (n + 1);
+        T.tile_pre = dpre + 2 * (n + 1);
+    }
+    tv::profile_count_call();
+    {
+        tv::StageScope sc(tv::kStageClear, s);
+        tv::launch_clear(b.meta, (int64_t)L.clear_end / 4, s);
+        tv::launch_set_word(b.meta + tv::kMetaMeshes, (uint32_t)c.meshes, s);
+    }
+    {
+        tv::StageScope sc(tv::kStageIngest, s);
+        tv::launch_ingest(T, b, s);
+    }
+    tv_status st = check_hip("ingest launch");
+    if (st) return st;
+    if (flags & TV_PATH_PER_TET) {
+        tv::StageScope sc(tv::kStageVoxelize, s);
+        for (const tv::MeshDesc &d : descs) {
+            tv::launch_clear(d.grid, (int64_t)d.g.n[0] * d.g.n[1] * d.g.words, s);
+            tv::launch_voxelize_per_tet(d, b, strict, s);
+        }
+        return check_hip("per-tet voxelize launch");
+    }
+    {
+        tv::StageScope sc(tv::kStageBin, s);
+        tv::launch_bin_count(T, b, s);
+        tv::launch_scan_tiles(T, b, s);
+        tv::launch_bin_scatter(T, b, s);
+        tv::launch_zero_shared_tiles(T, b, s);
+    }
+    if ((st = check_hip("binning launch"))) return st;
+    const int cus = device_cus();
+    {
+        tv::StageScope sc(tv::kStageVoxelize, s);
+        tv::launch_tile_voxelize(T, b, strict, 2 * cus, s);
+    }
+    {
+        tv::StageScope sc(tv::kStageLarge, s);
+        tv::launch_large_tets(T, b, strict, cus, s);
+    }
+    return check_hip("voxelize launch");
+}
+
+tv_status check_ws(void *ws, size_t ws_bytes, size_t need, uint32_t flags) {
     if (flags & ~kKnownFlags) return fail(TV_ERR_INVALID_ARG, "unknown flag bits 0x%x", flags);
     if (!ws || ((uintptr_t)ws & 255u))
         return fail(TV_ERR_WORKSPACE, "workspace null or not 256-byte aligned");
-    const size_t need = tv_workspace_bytes(nv, nt, dims, flags);
     if (ws_bytes < need)
         return fail(TV_ERR_WORKSPACE, "workspace of %zu bytes, need %zu", ws_bytes, need);
     return TV_OK;
 }
 
-tv_status check_bbox(const tv_bbox &bbox, tv::BoxD &box) {
-    for (int a = 0; a < 3; ++a) {
-        if (!isfinite(bbox.lo[a]) || !isfinite(bbox.hi[a]) || !(bbox.hi[a] > bbox.lo[a]))
-            return fail(TV_ERR_INVALID_ARG, "bbox axis %d: need finite lo < hi", a);
-        box.lo[a] = (double)bbox.lo[a];
-        box.ext[a] = (double)bbox.hi[a] - (double)bbox.lo[a];
-    }
-    return TV_OK;
+tv_status voxelize_one(const void *verts, uint32_t fmt, int64_t nv, const int32_t *tets, int64_t nt,
+                       tv_dims dims, const tv_bbox *bbox, uint32_t *grid, void *ws, size_t ws_bytes,
+                       void *stream, uint32_t flags) {
+    tv_status st = check_mesh(verts, fmt, nv, tets, nt, dims, bbox, grid, "");
+    if (st) return st;
+    if ((st = check_ws(ws, ws_bytes, tv_workspace_bytes(nv, nt, dims, flags), flags))) return st;
+    std::vector<tv::MeshDesc> descs(
+        1, make_desc(verts, fmt, nv, tets, nt, dims, bbox, grid, kMinTilesSingle));
+    const tv::CallSizes c = assign_bases(descs);
+    return run(descs, c, static_cast<uint8_t *>(ws), reinterpret_cast<hipStream_t>(stream), flags);
 }
 
-// Everything after ingest: binning, tile voxelization, large tets (or the
-// per-tet reference path).
-tv_status run_single(const int4 *q4, int64_t nv, const int32_t *tets32, int64_t nt, tv_dims dims,
-                     uint32_t *grid, const tv::TilePlan &p, const tv::WorkspaceLayout &L,
-                     uint8_t *ws, hipStream_t s, uint32_t flags) {
-    const tv::GridGeom g = make_geom(dims);
-    const tv::BinBuffers b = tv::bin_buffers(ws, L);
-    const int4 *tets = reinterpret_cast<const int4 *>(tets32);
-    const bool strict = (flags & TV_TIE_STRICT) != 0;
-    if (flags & TV_PATH_PER_TET) {
-        tv::StageScope sc(tv::kStageVoxelize, s);
-        tv::launch_clear(grid, (int64_t)tv_grid_words(dims), s);
-        tv::launch_voxelize_per_tet(q4, nv, tets, nt, g, grid, b.status, strict, s);
-        return check_hip("per-tet voxelize launch");
+bool batch_descs(const tv_mesh *meshes, int32_t n, std::vector<tv::MeshDesc> &descs,
+                 tv_status &st) {
+    descs.clear();
+    descs.reserve((size_t)n);
+    char which[48];
+    for (int32_t i = 0; i < n; ++i) {
+        const tv_mesh &m = meshes[i];
+        snprintf(which, sizeof which, "mesh %d: ", i);
+        st = check_mesh(m.verts, m.vert_format, m.nv, m.tets, m.nt, m.dims, &m.bbox, m.grid, which);
+        if (st) return false;
+        descs.push_back(make_desc(m.verts, m.vert_format, m.nv, m.tets, m.nt, m.dims, &m.bbox,
+                                  m.grid, kMinTilesBatch));
     }
-    {
-        tv::StageScope sc(tv::kStageBin, s);
-        tv::launch_bin_count(q4, nv, tets, nt, g, p, b, s);
-        tv::launch_scan_tiles(p, b, s);
-        tv::launch_bin_scatter(q4, nv, tets, nt, g, p, b, s);
-        tv::launch_zero_shared_tiles(g, p, b, grid, s);
-    }
-    tv_status st = check_hip("binning launch");
-    if (st) return st;
-    const int cus = device_cus();
-    {
-        tv::StageScope sc(tv::kStageVoxelize, s);
-        int64_t wgs = 2 * (int64_t)cus;
-        tv::launch_tile_voxelize(q4, tets, g, p, b, grid, strict, (int)wgs, s);
-    }
-    {
-        tv::StageScope sc(tv::kStageLarge, s);
-        tv::launch_large_tets(q4, tets, g, b, grid, strict, cus, s);
-    }
-    return check_hip("voxelize launch");
-}
-
-tv_status voxelize_common(const void *verts, bool fp32, const tv::BoxD *box, int64_t nv,
-                          const int32_t *tets, int64_t nt, tv_dims dims, uint32_t *grid, void *ws,
-                          hipStream_t s, uint32_t flags) {
-    const tv::TilePlan p = tv::plan_tiles(dims, kMinTiles);
-    const tv::WorkspaceLayout L = tv::single_layout(nv, nt, p);
-    uint8_t *w = static_cast<uint8_t *>(ws);
-    uint32_t *status = reinterpret_cast<uint32_t *>(w + L.status);
-    int4 *q4 = reinterpret_cast<int4 *>(w + L.q4);
-    tv::profile_count_call();
-    {
-        tv::StageScope sc(tv::kStageClear, s);
-        tv::launch_clear(status, (int64_t)(L.clear_end - L.status) / 4, s);
-    }
-    {
-        tv::StageScope sc(tv::kStageIngest, s);
-        if (fp32)
-            tv::launch_ingest_f32(static_cast<const float *>(verts), nv, *box, q4, status, s);
-        else
-            tv::launch_ingest_q32(static_cast<const int32_t *>(verts), nv, q4, status, s);
-    }
-    tv_status st = check_hip("ingest launch");
-    if (st) return st;
-    return run_single(q4, nv, tets, nt, dims, grid, p, L, w, s, flags);
+    st = TV_OK;
+    return true;
 }
 
 }  // namespace
@@ -173,46 +260,72 @@ size_t tv_grid_words(tv_dims d) {
 size_t tv_workspace_bytes(int64_t nv, int64_t nt, tv_dims dims, uint32_t flags) {
     (void)flags;
     if (nv < 0 || nt < 0 || !tv_grid_words(dims)) return 0;
-    return tv::single_layout(nv, nt, tv::plan_tiles(dims, kMinTiles)).total;
+    const tv::CallSizes c = {1, nv, nt, tv::plan_tiles(dims, kMinTilesSingle).ntiles};
+    return tv::layout(c).total;
 }
 
 tv_status tv_voxelize(const float *verts, int64_t nv, const int32_t *tets, int64_t nt,
                       tv_dims dims, tv_bbox bbox, uint32_t *grid, void *ws, size_t ws_bytes,
                       void *stream, uint32_t flags) {
-    tv_status st = check_common(nv, tets, nt, dims, grid, ws, ws_bytes, flags, verts);
-    if (st) return st;
-    tv::BoxD box;
-    if ((st = check_bbox(bbox, box))) return st;
-    return voxelize_common(verts, true, &box, nv, tets, nt, dims, grid, ws,
-                           reinterpret_cast<hipStream_t>(stream), flags);
+    return voxelize_one(verts, TV_VERTS_F32, nv, tets, nt, dims, &bbox, grid, ws, ws_bytes, stream,
+                        flags);
 }
 
 tv_status tv_voxelize_q(const int32_t *qverts, int64_t nv, const int32_t *tets, int64_t nt,
                         tv_dims dims, uint32_t *grid, void *ws, size_t ws_bytes, void *stream,
                         uint32_t flags) {
-    tv_status st = check_common(nv, tets, nt, dims, grid, ws, ws_bytes, flags, qverts);
-    if (st) return st;
-    return voxelize_common(qverts, false, nullptr, nv, tets, nt, dims, grid, ws,
-                           reinterpret_cast<hipStream_t>(stream), flags);
+    return voxelize_one(qverts, TV_VERTS_Q32, nv, tets, nt, dims, nullptr, grid, ws, ws_bytes,
+                        stream, flags);
+}
+
+size_t tv_batch_workspace_bytes(const tv_mesh *meshes, int32_t n, uint32_t flags) {
+    (void)flags;
+    if (!meshes || n <= 0) return 0;
+    std::vector<tv::MeshDesc> descs;
+    tv_status st;
+    if (!batch_descs(meshes, n, descs, st)) return 0;
+    return tv::layout(assign_bases(descs)).total;
+}
+
+tv_status tv_voxelize_batch(const tv_mesh *meshes, int32_t n, void *ws, size_t ws_bytes,
+                            void *stream, uint32_t flags) {
+    if (!meshes || n <= 0) return fail(TV_ERR_INVALID_ARG, "empty batch");
+    std::vector<tv::MeshDesc> descs;
+    tv_status st;
+    if (!batch_descs(meshes, n, descs, st)) return st;
+    const tv::CallSizes c = assign_bases(descs);
+    if (c.nt > kMaxTets) return fail(TV_ERR_INVALID_ARG, "batch has more than 2^28 tets");
+    if ((st = check_ws(ws, ws_bytes, tv::layout(c).total, flags))) return st;
+    return run(descs, c, static_cast<uint8_t *>(ws), reinterpret_cast<hipStream_t>(stream), flags);
 }
 
 tv_status tv_snap(const float *verts, int64_t nv, tv_bbox bbox, int32_t *q_out, void *stream) {
     if (nv < 0 || nv > INT32_MAX || (nv > 0 && (!verts || !q_out)))
         return fail(TV_ERR_INVALID_ARG, "bad snap arguments");
     tv::BoxD box;
-    tv_status st = check_bbox(bbox, box);
-    if (st) return st;
+    for (int a = 0; a < 3; ++a) {
+        if (!isfinite(bbox.lo[a]) || !isfinite(bbox.hi[a]) || !(bbox.hi[a] > bbox.lo[a]))
+            return fail(TV_ERR_INVALID_ARG, "bbox axis %d: need finite lo < hi", a);
+        box.lo[a] = (double)bbox.lo[a];
+        box.ext[a] = (double)bbox.hi[a] - (double)bbox.lo[a];
+    }
     tv::launch_snap_only(verts, nv, box, q_out, reinterpret_cast<hipStream_t>(stream));
     return check_hip("snap launch");
 }
 
 tv_status tv_fetch_status(const void *ws, int32_t mesh_index, void *stream) {
-    if (!ws || mesh_index < 0 || mesh_index >= tv::kStatusWords)
-        return fail(TV_ERR_INVALID_ARG, "bad workspace or mesh index %d", mesh_index);
+    if (!ws || mesh_index < 0) return fail(TV_ERR_INVALID_ARG, "bad workspace or mesh index");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    uint32_t word = 0;
+    uint32_t meshes = 0, word = 0;
     const uint8_t *w = static_cast<const uint8_t *>(ws);
-    if (hipMemcpyAsync(&word, w + tv::kStatusOffset + 4 * (size_t)mesh_index, 4,
+    if (hipMemcpyAsync(&meshes, w + 4 * tv::kMetaMeshes, 4, hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return fail(TV_ERR_HIP, "reading the workspace header failed");
+    if ((uint32_t)mesh_index >= meshes)
+        return fail(TV_ERR_INVALID_ARG, "mesh index %d outside the last call's %u meshes",
+                    mesh_index, meshes);
+    if (hipMemcpyAsync(&word, w + 4 * tv::kMetaWords + 4 * (size_t)mesh_index, 4,
                        hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         return fail(TV_ERR_HIP, "reading the status word failed");

@@ -20,48 +20,75 @@ struct TilePlan {
     int32_t lx, ly, lw;
     int32_t ntx, nty, ntz;  // tiles per axis
     int64_t ntiles;
+};
+
+constexpr int32_t kFmtF32 = 0;
+constexpr int32_t kFmtQ32 = 1;
+
+// Everything the kernels need to know about one mesh of a call.
+struct MeshDesc {
+    const void *verts;   // fp32 or int32 [nv][3]
+    const int4 *tets;    // [nt]
+    uint32_t *grid;      // output words
+    int64_t nv, nt;
+    int64_t vert_base;   // first lattice record of the mesh in the call's q4 array
+    int64_t tet_base;    // global index of tets[0] among the call's tets
+    int64_t tile_base;   // global index of the mesh's first tile
+    BoxD box;
+    GridGeom g;
+    TilePlan p;
+    int32_t fmt;         // kFmtF32 / kFmtQ32
+    int32_t mesh;        // index (status word)
+};
+
+// The meshes of one call.  A single mesh travels by value in `one`; a batch
+// lives in device memory with prefix sums over vertices, tets and tiles
+// (each [n + 1]) that map a global index to its mesh.
+struct MeshTable {
+    const MeshDesc *descs;
+    const int64_t *vert_pre;
+    const int64_t *tet_pre;
+    const int64_t *tile_pre;
+    int32_t n;
     int32_t chunk;      // pieces per chunk (one workgroup task)
-    int32_t strip;      // columns per lane task
+    int32_t strip;      // kept columns per lane task
     int32_t piece_cap;  // tets meeting more tiles than this go to the large-tet kernel
+    int64_t nv_total, nt_total, ntiles_total;
+    MeshDesc one;
 };
 
 // meta[] slots
 constexpr int kMetaQueue = 0;   // next chunk to hand out
 constexpr int kMetaBig = 1;     // number of large tets
 constexpr int kMetaChunks = 2;  // total chunks
+constexpr int kMetaMeshes = 3;  // meshes of the last call (status words in use)
 
 // Device buffers of the binned pipeline (all inside the caller's workspace).
 struct BinBuffers {
-    uint32_t *status;       // per-mesh status word
     uint32_t *meta;         // counters (kMeta*)
+    uint32_t *status;       // one status word per mesh
     uint32_t *tile_count;   // [ntiles] pieces per tile
     uint32_t *tile_cursor;  // [ntiles] fill cursor of the scatter pass
     uint32_t *tile_off;     // [ntiles + 1] first piece slot per tile
     uint32_t *chunk_off;    // [ntiles + 1] first chunk per tile
-    uint32_t *pieces;       // [nt * piece_cap] tet ids sorted by tile
-    uint32_t *big;          // [nt] large tets
+    uint32_t *pieces;       // [nt * piece_cap] global tet ids sorted by tile
+    uint32_t *big;          // [nt] large tets (global ids)
+    int4 *q4;               // [nv] lattice vertices (.w = invalid flag)
 };
 
-void launch_ingest_f32(const float *v, int64_t nv, const BoxD &box, int4 *q4, uint32_t *status,
-                       hipStream_t s);
-void launch_ingest_q32(const int32_t *q, int64_t nv, int4 *q4, uint32_t *status, hipStream_t s);
+void launch_ingest(const MeshTable &T, const BinBuffers &b, hipStream_t s);
 void launch_snap_only(const float *v, int64_t nv, const BoxD &box, int32_t *q, hipStream_t s);
 void launch_clear(uint32_t *p, int64_t nwords, hipStream_t s);
-void launch_bin_count(const int4 *q4, int64_t nv, const int4 *tets, int64_t nt, const GridGeom &g,
-                      const TilePlan &p, const BinBuffers &b, hipStream_t s);
-void launch_scan_tiles(const TilePlan &p, const BinBuffers &b, hipStream_t s);
-void launch_bin_scatter(const int4 *q4, int64_t nv, const int4 *tets, int64_t nt,
-                        const GridGeom &g, const TilePlan &p, const BinBuffers &b, hipStream_t s);
-void launch_zero_shared_tiles(const GridGeom &g, const TilePlan &p, const BinBuffers &b,
-                              uint32_t *grid, hipStream_t s);
-void launch_tile_voxelize(const int4 *q4, const int4 *tets, const GridGeom &g, const TilePlan &p,
-                          const BinBuffers &b, uint32_t *grid, bool strict, int workgroups,
+void launch_set_word(uint32_t *p, uint32_t value, hipStream_t s);
+void launch_bin_count(const MeshTable &T, const BinBuffers &b, hipStream_t s);
+void launch_scan_tiles(const MeshTable &T, const BinBuffers &b, hipStream_t s);
+void launch_bin_scatter(const MeshTable &T, const BinBuffers &b, hipStream_t s);
+void launch_zero_shared_tiles(const MeshTable &T, const BinBuffers &b, hipStream_t s);
+void launch_tile_voxelize(const MeshTable &T, const BinBuffers &b, bool strict, int workgroups,
                           hipStream_t s);
-void launch_large_tets(const int4 *q4, const int4 *tets, const GridGeom &g, const BinBuffers &b,
-                       uint32_t *grid, bool strict, int workgroups, hipStream_t s);
-void launch_voxelize_per_tet(const int4 *q4, int64_t nv, const int4 *tets, int64_t nt,
-                             const GridGeom &g, uint32_t *grid, uint32_t *status, bool strict,
-                             hipStream_t s);
+void launch_large_tets(const MeshTable &T, const BinBuffers &b, bool strict, int workgroups,
+                       hipStream_t s);
+void launch_voxelize_per_tet(const MeshDesc &d, const BinBuffers &b, bool strict, hipStream_t s);
 int tile_max_words();
 
 }  // namespace tv

@@ -1,25 +1,46 @@
 // Device kernels of the voxelizer: ingest (snap / range check), binning of
 // tets into grid tiles, the tile voxelization kernel, the large-tet kernel
-// and the per-tet reference kernel.
+// and the per-tet reference kernel.  Every kernel serves one mesh or a batch
+// of meshes of uneven size in the same launch (a MeshTable maps global
+// vertex, tet and tile indices to their mesh).
 //
-// Work decomposition.  The grid is cut into tiles of tx * ty columns and tw
-// words (32*tw voxels) of each column.  A tet meets the tiles that its
-// candidate box (the voxel centers inside its bounding box, Section 3
+// Work decomposition.  Each grid is cut into tiles of 2^lx x 2^ly columns and
+// 2^lw words (32 * 2^lw voxels) of each column.  A tet meets the tiles that
+// its candidate box (the voxel centers inside its bounding box, Section 3
 // "Voxelization") overlaps; each (tet, tile) pair is a "piece".  Pieces are
 // counting-sorted by tile, and each tile's piece list is cut into chunks.
 // One workgroup takes one chunk: it builds the chunk's pieces' face data in
-// LDS, splits the pieces' columns into fixed-length strips so that all lanes
-// get equal work, decides every column's z span exactly and ORs it into a
-// tile bitmap in LDS.  A tile covered by one chunk is then written out with
-// plain stores (zeros included, so the grid needs no separate clear); a
-// tile covered by several chunks was zeroed beforehand and each chunk ORs
-// its non-zero words into it.  Tets whose candidate box meets more tiles
-// than a fixed cap are set aside and handled by a separate kernel that
-// spreads one tet's columns over a whole workgroup and ORs into the grid.
+// LDS, keeps per row only the columns the tet's xy projection can reach,
+// splits those columns into fixed-length strips so that all lanes get equal
+// work, decides every column's z span exactly and ORs it into a tile bitmap
+// in LDS.  A tile covered by one chunk is then written out with plain stores
+// (zeros included, so grids need no separate clear); a tile covered by
+// several chunks was zeroed beforehand and each chunk ORs its non-zero words
+// into it.  Tets whose candidate box meets more tiles than a fixed cap are
+// set aside and handled by a separate kernel that spreads one tet's columns
+// over a whole workgroup and ORs into the grid.
 #include "tv_common.h"
 #include "tv_kernels.h"
 
 namespace tv {
+
+// --------------------------------------------------------- mesh lookup
+
+// Last m in [0, n) with pre[m] <= x (pre is non-decreasing, pre[0] = 0).
+__device__ __forceinline__ int32_t find_mesh(const int64_t *__restrict__ pre, int32_t n,
+                                             int64_t x) {
+    int32_t lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (pre[mid] <= x) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ const MeshDesc &mesh_desc(const MeshTable &T, int32_t m) {
+    return T.n == 1 ? T.one : T.descs[m];
+}
 
 // ----------------------------------------------------------------- ingest
 
@@ -38,18 +59,31 @@ __device__ __forceinline__ bool snap_coord(float v, double lo, double ext, int32
     return in;
 }
 
-// Snap into padded int4 records; the .w lane marks a vertex that is NaN or
-// off the lattice range -- such vertices void their tets.
-__global__ void k_ingest_f32(const float *__restrict__ v, int64_t nv, BoxD box,
-                             int4 *__restrict__ q4, uint32_t *__restrict__ status) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nv) return;
+// Every vertex of every mesh of the call -> padded int4 lattice record; the
+// .w lane marks a vertex that is NaN or off the lattice range (such vertices
+// void their tets and raise the mesh's status).
+__global__ void k_ingest(MeshTable T, BinBuffers b) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= T.nv_total) return;
+    const int32_t m = T.n == 1 ? 0 : find_mesh(T.vert_pre, T.n, v);
+    const MeshDesc &d = mesh_desc(T, m);
+    const int64_t i = v - d.vert_base;
     int32_t q[3];
     bool ok = true;
+    if (d.fmt == kFmtF32) {
+        const float *vf = static_cast<const float *>(d.verts);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) ok = snap_coord(v[3 * i + a], box.lo[a], box.ext[a], q[a]) && ok;
-    q4[i] = make_int4(q[0], q[1], q[2], ok ? 0 : 1);
-    if (!ok) atomicOr(status, kStatusRange);
+        for (int a = 0; a < 3; ++a) ok = snap_coord(vf[3 * i + a], d.box.lo[a], d.box.ext[a], q[a]) && ok;
+    } else {
+        const int32_t *vq = static_cast<const int32_t *>(d.verts);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            q[a] = vq[3 * i + a];
+            ok = ok && q[a] >= kQMin && q[a] <= kQMax;
+        }
+    }
+    b.q4[v] = make_int4(q[0], q[1], q[2], ok ? 0 : 1);
+    if (!ok) atomicOr(b.status + d.mesh, kStatusRange);
 }
 
 // Snap into a plain [nv][3] int32 array (INT32_MIN marks a bad vertex).
@@ -63,18 +97,6 @@ __global__ void k_snap_only(const float *__restrict__ v, int64_t nv, BoxD box,
     for (int a = 0; a < 3; ++a) ok = snap_coord(v[3 * i + a], box.lo[a], box.ext[a], c[a]) && ok;
 #pragma unroll
     for (int a = 0; a < 3; ++a) q[3 * i + a] = ok ? c[a] : INT32_MIN;
-}
-
-// int32 lattice coordinates -> padded int4 with the same range check.
-__global__ void k_ingest_q32(const int32_t *__restrict__ qin, int64_t nv, int4 *__restrict__ q4,
-                             uint32_t *__restrict__ status) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nv) return;
-    const int32_t x = qin[3 * i], y = qin[3 * i + 1], z = qin[3 * i + 2];
-    const bool ok = x >= kQMin && x <= kQMax && y >= kQMin && y <= kQMax && z >= kQMin &&
-                    z <= kQMax;
-    q4[i] = make_int4(x, y, z, ok ? 0 : 1);
-    if (!ok) atomicOr(status, kStatusRange);
 }
 
 // Zero `n` words at `p` (4-byte aligned) with 16-byte stores where possible.
@@ -91,24 +113,9 @@ __global__ void k_clear(uint32_t *__restrict__ p, int64_t n) {
     if (tid < n - tail0) p[tail0 + tid] = 0u;
 }
 
-// ------------------------------------------------------------- tet gather
+__global__ void k_set_word(uint32_t *p, uint32_t value) { *p = value; }
 
-// Gathers tet t's vertices; false for a bad index (flagged in `status`
-// unless it is null) and for a vertex that failed ingest (flagged there).
-__device__ __forceinline__ bool gather_tet(const int4 *__restrict__ q4, int64_t nv,
-                                           const int4 *__restrict__ tets, int64_t t,
-                                           uint32_t *status, int4 V[4]) {
-    const int4 T = tets[t];
-    if (!index_ok(T.x, nv) || !index_ok(T.y, nv) || !index_ok(T.z, nv) || !index_ok(T.w, nv)) {
-        if (status) atomicOr(status, kStatusIndex);
-        return false;
-    }
-    V[0] = q4[T.x];
-    V[1] = q4[T.y];
-    V[2] = q4[T.z];
-    V[3] = q4[T.w];
-    return (V[0].w | V[1].w | V[2].w | V[3].w) == 0;
-}
+// ------------------------------------------------------------- tet gather
 
 // Six times the signed volume (Lemma 1.1), exact in double (see tv_common.h).
 __device__ __forceinline__ double six_volume(const int4 V[4]) {
@@ -116,6 +123,25 @@ __device__ __forceinline__ double six_volume(const int4 V[4]) {
     const double bx = V[2].x - V[0].x, by = V[2].y - V[0].y, bz = V[2].z - V[0].z;
     const double cx = V[3].x - V[0].x, cy = V[3].y - V[0].y, cz = V[3].z - V[0].z;
     return ax * (by * cz - bz * cy) - ay * (bx * cz - bz * cx) + az * (bx * cy - by * cx);
+}
+
+// Gathers the vertices of local tet `tl` of mesh d; false for a bad index
+// (flagged in the mesh's status word when `status` is not null) and for a
+// vertex that failed ingest (flagged there).
+__device__ __forceinline__ bool gather_tet(const MeshDesc &d, const int4 *__restrict__ q4,
+                                           int64_t tl, uint32_t *status, int4 V[4]) {
+    const int4 T = d.tets[tl];
+    if (!index_ok(T.x, d.nv) || !index_ok(T.y, d.nv) || !index_ok(T.z, d.nv) ||
+        !index_ok(T.w, d.nv)) {
+        if (status) atomicOr(status + d.mesh, kStatusIndex);
+        return false;
+    }
+    const int4 *q = q4 + d.vert_base;
+    V[0] = q[T.x];
+    V[1] = q[T.y];
+    V[2] = q[T.z];
+    V[3] = q[T.w];
+    return (V[0].w | V[1].w | V[2].w | V[3].w) == 0;
 }
 
 struct TileRange {
@@ -140,16 +166,14 @@ __device__ __forceinline__ uint32_t tile_id(int32_t x, int32_t y, int32_t z, con
 
 // Shared front of both binning passes: the tet's tile range and piece
 // count (0 when it contributes nothing).
-__device__ __forceinline__ int32_t tet_pieces(const int4 *__restrict__ q4, int64_t nv,
-                                              const int4 *__restrict__ tets, int64_t t,
-                                              const GridGeom &g, const TilePlan &p,
-                                              uint32_t *status, TileRange &r) {
+__device__ __forceinline__ int32_t tet_pieces(const MeshDesc &d, const int4 *__restrict__ q4,
+                                              int64_t tl, uint32_t *status, TileRange &r) {
     int4 V[4];
-    if (!gather_tet(q4, nv, tets, t, status, V)) return 0;
+    if (!gather_tet(d, q4, tl, status, V)) return 0;
     int32_t lo[3], hi[3];
-    if (!candidate_box(V[0], V[1], V[2], V[3], g, lo, hi)) return 0;
+    if (!candidate_box(V[0], V[1], V[2], V[3], d.g, lo, hi)) return 0;
     if (six_volume(V) == 0.0) return 0;
-    r = tile_range(lo, hi, p);
+    r = tile_range(lo, hi, d.p);
     return (r.x1 - r.x0 + 1) * (r.y1 - r.y0 + 1) * (r.z1 - r.z0 + 1);
 }
 
@@ -161,7 +185,7 @@ __device__ __forceinline__ int32_t tet_pieces(const int4 *__restrict__ q4, int64
 // which mostly share tiles, thus cost one global atomic per workgroup and
 // tile instead of one per piece.
 constexpr int kBinThreads = 256;
-constexpr int kHashSlots = 4096;  // >= 2 * kBinThreads * kPieceCapMax
+constexpr int kHashSlots = 4096;  // >= 2 * kBinThreads * kPieceCapMax: load <= 1/2
 constexpr int kPieceCapMax = 8;
 constexpr uint32_t kEmptyKey = 0xffffffffu;
 
@@ -175,9 +199,7 @@ __device__ __forceinline__ uint32_t hash_insert(uint32_t *keys, uint32_t key) {
 }
 
 template <bool kScatter>
-__global__ void __launch_bounds__(kBinThreads)
-    k_bin(const int4 *__restrict__ q4, int64_t nv, const int4 *__restrict__ tets, int64_t nt,
-          GridGeom g, TilePlan p, BinBuffers b) {
+__global__ void __launch_bounds__(kBinThreads) k_bin(MeshTable T, BinBuffers b) {
     __shared__ uint32_t s_key[kHashSlots];
     __shared__ uint32_t s_cnt[kHashSlots];  // count, then (pass 2) global slot base
     __shared__ uint32_t s_ref[kBinThreads * kPieceCapMax];  // slot << 16 | rank
@@ -188,22 +210,27 @@ __global__ void __launch_bounds__(kBinThreads)
     }
     __syncthreads();
     const int64_t t = (int64_t)blockIdx.x * kBinThreads + tid;
-    TileRange r = {0, -1, 0, -1, 0, -1};
     int32_t np = 0;
-    // status flags are raised by the counting pass only
-    if (t < nt) np = tet_pieces(q4, nv, tets, t, g, p, kScatter ? nullptr : b.status, r);
-    if (np > p.piece_cap) {
-        if (!kScatter) b.big[atomicAdd(&b.meta[kMetaBig], 1u)] = (uint32_t)t;
-        np = 0;
-    }
-    const int32_t ny_ = r.y1 - r.y0 + 1, nz_ = r.z1 - r.z0 + 1;
-    for (int32_t k = 0; k < np; ++k) {
-        const int32_t dz = k % nz_, rest = k / nz_;
-        const int32_t dy = rest % ny_, dx = rest / ny_;
-        const uint32_t key = tile_id(r.x0 + dx, r.y0 + dy, r.z0 + dz, p);
-        const uint32_t h = hash_insert(s_key, key);
-        const uint32_t rank = atomicAdd(s_cnt + h, 1u);
-        s_ref[tid * kPieceCapMax + k] = (h << 16) | rank;
+    if (t < T.nt_total) {
+        const int32_t m = T.n == 1 ? 0 : find_mesh(T.tet_pre, T.n, t);
+        const MeshDesc &d = mesh_desc(T, m);
+        TileRange r = {0, -1, 0, -1, 0, -1};
+        // status flags are raised by the counting pass only
+        np = tet_pieces(d, b.q4, t - d.tet_base, kScatter ? nullptr : b.status, r);
+        if (np > T.piece_cap) {
+            if (!kScatter) b.big[atomicAdd(&b.meta[kMetaBig], 1u)] = (uint32_t)t;
+            np = 0;
+        }
+        const uint32_t tbase = (uint32_t)d.tile_base;
+        const int32_t ny_ = r.y1 - r.y0 + 1, nz_ = r.z1 - r.z0 + 1;
+        for (int32_t k = 0; k < np; ++k) {
+            const int32_t dz = k % nz_, rest = k / nz_;
+            const int32_t dy = rest % ny_, dx = rest / ny_;
+            const uint32_t key = tbase + tile_id(r.x0 + dx, r.y0 + dy, r.z0 + dz, d.p);
+            const uint32_t h = hash_insert(s_key, key);
+            const uint32_t rank = atomicAdd(s_cnt + h, 1u);
+            s_ref[tid * kPieceCapMax + k] = (h << 16) | rank;
+        }
     }
     __syncthreads();
     for (int i = tid; i < kHashSlots; i += kBinThreads) {
@@ -223,10 +250,11 @@ __global__ void __launch_bounds__(kBinThreads)
 // Exclusive scan of the per-tile piece counts (one workgroup of 1024
 // threads, any tile count): tile_off[t] is the first piece slot of tile t;
 // chunk_off[t] the first chunk; meta[kMetaChunks] the chunk total.
-__global__ void __launch_bounds__(1024) k_scan_tiles(TilePlan p, BinBuffers b) {
+__global__ void __launch_bounds__(1024) k_scan_tiles(MeshTable T, BinBuffers b) {
     __shared__ uint32_t s_cnt[1024], s_chk[1024];
     __shared__ uint32_t s_base_cnt, s_base_chk;
-    const uint32_t nt = (uint32_t)p.ntiles;
+    const uint32_t nt = (uint32_t)T.ntiles_total;
+    const uint32_t chunk = (uint32_t)T.chunk;
     const int tid = threadIdx.x;
     if (tid == 0) {
         s_base_cnt = 0;
@@ -236,17 +264,17 @@ __global__ void __launch_bounds__(1024) k_scan_tiles(TilePlan p, BinBuffers b) {
     for (uint32_t base = 0; base < nt; base += 1024) {
         const uint32_t i = base + tid;
         const uint32_t c = i < nt ? b.tile_count[i] : 0u;
-        const uint32_t k = i < nt ? (c == 0 ? 1u : (c + p.chunk - 1) / p.chunk) : 0u;
+        const uint32_t k = i < nt ? (c == 0 ? 1u : (c + chunk - 1) / chunk) : 0u;
         s_cnt[tid] = c;
         s_chk[tid] = k;
         __syncthreads();
         // Hillis-Steele inclusive scan
         for (int off = 1; off < 1024; off <<= 1) {
             const uint32_t a = tid >= off ? s_cnt[tid - off] : 0u;
-            const uint32_t d = tid >= off ? s_chk[tid - off] : 0u;
+            const uint32_t e = tid >= off ? s_chk[tid - off] : 0u;
             __syncthreads();
             s_cnt[tid] += a;
-            s_chk[tid] += d;
+            s_chk[tid] += e;
             __syncthreads();
         }
         if (i < nt) {
@@ -267,26 +295,33 @@ __global__ void __launch_bounds__(1024) k_scan_tiles(TilePlan p, BinBuffers b) {
     }
 }
 
-// Global word index of word w of tile-local column cl in tile `tile`.
-__device__ __forceinline__ int64_t tile_word(uint32_t tile, int32_t cl, int32_t w,
-                                             const GridGeom &g, const TilePlan &p) {
-    const int32_t tz = (int32_t)(tile % (uint32_t)p.ntz);
-    const uint32_t txy = tile / (uint32_t)p.ntz;
+// Tile origin (voxel indices) of local tile `lt` of a mesh.
+struct TileOrigin {
+    int32_t i0, j0, k0;
+};
+
+__device__ __forceinline__ TileOrigin tile_origin(uint32_t lt, const TilePlan &p) {
+    const int32_t tz = (int32_t)(lt % (uint32_t)p.ntz);
+    const uint32_t txy = lt / (uint32_t)p.ntz;
     const int32_t ty = (int32_t)(txy % (uint32_t)p.nty), tx = (int32_t)(txy / (uint32_t)p.nty);
-    const int64_t i = ((int64_t)tx << p.lx) + (cl >> p.ly);
-    const int64_t j = ((int64_t)ty << p.ly) + (cl & ((1 << p.ly) - 1));
-    return (i * g.n[1] + j) * g.words + ((int64_t)tz << p.lw) + w;
+    return {tx << p.lx, ty << p.ly, tz << (p.lw + 5)};
 }
 
-// Zero the tiles that several chunks will OR into.
-__global__ void k_zero_shared_tiles(GridGeom g, TilePlan p, BinBuffers b, uint32_t *grid) {
+// Zero the tiles that several chunks will OR into (one workgroup per tile).
+__global__ void k_zero_shared_tiles(MeshTable T, BinBuffers b) {
     const uint32_t tile = blockIdx.x;
-    if (tile >= (uint32_t)p.ntiles) return;
+    if (tile >= (uint32_t)T.ntiles_total) return;
     if (b.chunk_off[tile + 1] - b.chunk_off[tile] <= 1) return;
-    const int32_t tw = 1 << p.lw;
-    const int32_t nwords = (1 << (p.lx + p.ly)) * tw;
-    for (int32_t x = threadIdx.x; x < nwords; x += blockDim.x)
-        grid[tile_word(tile, x >> p.lw, x & (tw - 1), g, p)] = 0u;
+    const int32_t m = T.n == 1 ? 0 : find_mesh(T.tile_pre, T.n, (int64_t)tile);
+    const MeshDesc &d = mesh_desc(T, m);
+    const TileOrigin o = tile_origin(tile - (uint32_t)d.tile_base, d.p);
+    const int32_t lw = d.p.lw, ly = d.p.ly;
+    const int32_t nwords = (1 << (d.p.lx + ly + lw));
+    for (int32_t x = threadIdx.x; x < nwords; x += blockDim.x) {
+        const int32_t cl = x >> lw;
+        const int64_t i = o.i0 + (cl >> ly), j = o.j0 + (cl & ((1 << ly) - 1));
+        d.grid[(i * d.g.n[1] + j) * d.g.words + (o.k0 >> 5) + (x & ((1 << lw) - 1))] = 0u;
+    }
 }
 
 // ------------------------------------------------------ tile voxelization
@@ -305,7 +340,7 @@ struct PieceRec {
     uint16_t ncols;     // columns kept after culling (<= 1024)
 };
 
-// z span [lo, hi) (box-relative) of column (di, dj) of a piece.
+// z span [lo, hi) (box-relative) of column (di, dj) of a box.
 __device__ __forceinline__ void column_span(const Face f[4], uint32_t lower, double di, double dj,
                                             int32_t nk, double nkd, int32_t &lo, int32_t &hi) {
     lo = 0;
@@ -335,12 +370,11 @@ __device__ __forceinline__ void row_columns(const double vx[4], const double vy[
         for (int c = a + 1; c < 4; ++c) {
             const double da = vx[a] - cx, dc = vx[c] - cx;
             if (da * dc <= 0.0) {  // the segment meets the plane (or lies in it)
-                double y;
                 if (vx[a] == vx[c]) {
                     ylo = fmin(ylo, fmin(vy[a], vy[c]));
                     yhi = fmax(yhi, fmax(vy[a], vy[c]));
                 } else {
-                    y = vy[a] + (vy[c] - vy[a]) * (da / (vx[a] - vx[c]));
+                    const double y = vy[a] + (vy[c] - vy[a]) * (da / (vx[a] - vx[c]));
                     ylo = fmin(ylo, y);
                     yhi = fmax(yhi, y);
                 }
@@ -353,21 +387,50 @@ __device__ __forceinline__ void row_columns(const double vx[4], const double vy[
     j1 = (int32_t)floor((yhi + 1.0 - S) * inv);
 }
 
+// Exclusive scan of v[0..255] in place by the first wave (4 values per lane);
+// writes the total to v[256].  With `first_over`, also stores the index of
+// the first entry whose end (offset + value) exceeds `cap` (256 if none).
+__device__ __forceinline__ void scan256_wave0(uint32_t *v, int tid, uint32_t *first_over,
+                                              uint32_t cap) {
+    if (tid < 64) {
+        const uint32_t v0 = v[4 * tid], v1 = v[4 * tid + 1], v2 = v[4 * tid + 2],
+                       v3 = v[4 * tid + 3];
+        const uint32_t sum = v0 + v1 + v2 + v3;
+        uint32_t incl = sum;
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t o = __shfl_up(incl, off);
+            if (tid >= off) incl += o;
+        }
+        const uint32_t ex = incl - sum;
+        const uint32_t e[4] = {ex, ex + v0, ex + v0 + v1, ex + v0 + v1 + v2};
+        const uint32_t w[4] = {v0, v1, v2, v3};
+        uint32_t first = kTileThreads;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            v[4 * tid + q] = e[q];
+            if (e[q] + w[q] > cap) first = min(first, (uint32_t)(4 * tid + q));
+        }
+        if (first_over) {
+            for (int off = 32; off > 0; off >>= 1)
+                first = min(first, (uint32_t)__shfl_xor((int)first, off));
+            if (tid == 0) *first_over = first;
+        }
+        if (tid == 63) v[kTileThreads] = incl;
+    }
+}
+
 __global__ void __launch_bounds__(kTileThreads)
-    k_tile_voxelize(const int4 *__restrict__ q4, const int4 *__restrict__ tets, GridGeom g,
-                    TilePlan p, BinBuffers b, uint32_t *__restrict__ grid, int strict) {
+    k_tile_voxelize(MeshTable T, BinBuffers b, int strict) {
     __shared__ uint32_t s_bits[kMaxTileWords];
     __shared__ PieceRec s_rec[kTileThreads];
     __shared__ uint32_t s_row[kRowPool];  // j0 (8 bits) | count (8 bits) | prefix (16 bits)
     __shared__ uint32_t s_soff[kTileThreads + 1];
     __shared__ uint32_t s_roff[kTileThreads + 1];
     __shared__ uint32_t s_chunk, s_tile, s_p0, s_p1, s_shared, s_nb;
+    __shared__ int32_t s_mesh;
 
     const int tid = threadIdx.x;
-    const int32_t tw = 1 << p.lw;
-    const int32_t tcols = 1 << (p.lx + p.ly);
-    const int32_t nwords = tcols * tw;
-    const uint32_t strip = (uint32_t)p.strip;
+    const uint32_t strip = (uint32_t)T.strip;
     const uint32_t total = b.meta[kMetaChunks];
 
     for (;;) {
@@ -376,7 +439,7 @@ __global__ void __launch_bounds__(kTileThreads)
             s_chunk = c;
             if (c < total) {
                 // tile = last t with chunk_off[t] <= c
-                uint32_t lo = 0, hi = (uint32_t)p.ntiles;  // chunk_off[lo] <= c < chunk_off[hi]
+                uint32_t lo = 0, hi = (uint32_t)T.ntiles_total;  // chunk_off[lo] <= c < chunk_off[hi]
                 while (hi - lo > 1) {
                     const uint32_t mid = (lo + hi) >> 1;
                     if (b.chunk_off[mid] <= c) lo = mid;
@@ -386,21 +449,27 @@ __global__ void __launch_bounds__(kTileThreads)
                 const uint32_t nchunks = b.chunk_off[lo + 1] - b.chunk_off[lo];
                 const uint32_t pb = b.tile_off[lo], pe = b.tile_off[lo + 1];
                 s_tile = lo;
-                s_p0 = min(pe, pb + k * (uint32_t)p.chunk);
-                s_p1 = min(pe, pb + (k + 1) * (uint32_t)p.chunk);
+                s_p0 = min(pe, pb + k * (uint32_t)T.chunk);
+                s_p1 = min(pe, pb + (k + 1) * (uint32_t)T.chunk);
                 s_shared = nchunks > 1 ? 1u : 0u;
+                s_mesh = T.n == 1 ? 0 : find_mesh(T.tile_pre, T.n, (int64_t)lo);
             }
         }
         __syncthreads();
         if (s_chunk >= total) break;
         const uint32_t tile = s_tile, p1 = s_p1;
+        const MeshDesc &d = mesh_desc(T, s_mesh);
+        const GridGeom g = d.g;
+        const TilePlan p = d.p;
+        const int4 *__restrict__ q4 = b.q4 + d.vert_base;
+        const int4 *__restrict__ tets = d.tets;
+        const uint32_t tbase = (uint32_t)d.tet_base;
+        const int32_t tw = 1 << p.lw;
+        const int32_t nwords = (1 << (p.lx + p.ly)) * tw;
         for (int32_t x = tid; x < nwords; x += kTileThreads) s_bits[x] = 0u;
 
-        // tile origin in voxel indices
-        const int32_t tz = (int32_t)(tile % (uint32_t)p.ntz);
-        const uint32_t txy = tile / (uint32_t)p.ntz;
-        const int32_t ty = (int32_t)(txy % (uint32_t)p.nty), tx = (int32_t)(txy / (uint32_t)p.nty);
-        const int32_t ti0 = tx << p.lx, tj0 = ty << p.ly, tk0 = tz << (p.lw + 5);
+        const TileOrigin o = tile_origin(tile - (uint32_t)d.tile_base, p);
+        const int32_t ti0 = o.i0, tj0 = o.j0, tk0 = o.k0;
         const int32_t ti1 = ti0 + (1 << p.lx) - 1, tj1 = tj0 + (1 << p.ly) - 1;
         const int32_t tk1 = min(tk0 + (tw << 5) - 1, g.n[2] - 1);
 
@@ -412,9 +481,8 @@ __global__ void __launch_bounds__(kTileThreads)
             double vx[4], vy[4];
             uint32_t nrows = 0;
             if (pi < p1) {
-                const uint32_t t = b.pieces[pi];
-                const int4 T = tets[t];
-                const int4 A = q4[T.x], B = q4[T.y], C = q4[T.z], D = q4[T.w];
+                const int4 Tt = tets[b.pieces[pi] - tbase];
+                const int4 A = q4[Tt.x], B = q4[Tt.y], C = q4[Tt.z], D = q4[Tt.w];
                 vx[0] = A.x; vx[1] = B.x; vx[2] = C.x; vx[3] = D.x;
                 vy[0] = A.y; vy[1] = B.y; vy[2] = C.y; vy[3] = D.y;
                 candidate_box(A, B, C, D, g, lo, hi);
@@ -449,29 +517,9 @@ __global__ void __launch_bounds__(kTileThreads)
             // every batch makes progress)
             s_roff[tid] = nrows;
             __syncthreads();
-            if (tid < 64) {
-                const uint32_t v0 = s_roff[4 * tid], v1 = s_roff[4 * tid + 1],
-                               v2 = s_roff[4 * tid + 2], v3 = s_roff[4 * tid + 3];
-                const uint32_t sum = v0 + v1 + v2 + v3;
-                uint32_t incl = sum;
-                for (int off = 1; off < 64; off <<= 1) {
-                    const uint32_t o = __shfl_up(incl, off);
-                    if (tid >= off) incl += o;
-                }
-                const uint32_t ex = incl - sum;
-                const uint32_t e[4] = {ex, ex + v0, ex + v0 + v1, ex + v0 + v1 + v2};
-                const uint32_t v[4] = {v0, v1, v2, v3};
-                uint32_t first_over = kTileThreads;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    s_roff[4 * tid + q] = e[q];
-                    if (e[q] + v[q] > (uint32_t)kRowPool) first_over = min(first_over, (uint32_t)(4 * tid + q));
-                }
-                for (int off = 32; off > 0; off >>= 1) first_over = min(first_over, (uint32_t)__shfl_xor((int)first_over, off));
-                if (tid == 0) s_nb = min(first_over, p1 - pb);
-            }
+            scan256_wave0(s_roff, tid, &s_nb, (uint32_t)kRowPool);
             __syncthreads();
-            const uint32_t nb = s_nb;
+            const uint32_t nb = min(s_nb, p1 - pb);
             // phase 1c: per-row column ranges of the pieces in this batch
             uint32_t nstrips = 0;
             if ((uint32_t)tid < nb && nrows) {
@@ -496,22 +544,7 @@ __global__ void __launch_bounds__(kTileThreads)
             // phase 2: exclusive scan of strip counts
             s_soff[tid] = nstrips;
             __syncthreads();
-            if (tid < 64) {
-                const uint32_t v0 = s_soff[4 * tid], v1 = s_soff[4 * tid + 1],
-                               v2 = s_soff[4 * tid + 2], v3 = s_soff[4 * tid + 3];
-                const uint32_t sum = v0 + v1 + v2 + v3;
-                uint32_t incl = sum;
-                for (int off = 1; off < 64; off <<= 1) {
-                    const uint32_t o = __shfl_up(incl, off);
-                    if (tid >= off) incl += o;
-                }
-                const uint32_t ex = incl - sum;
-                s_soff[4 * tid] = ex;
-                s_soff[4 * tid + 1] = ex + v0;
-                s_soff[4 * tid + 2] = ex + v0 + v1;
-                s_soff[4 * tid + 3] = ex + v0 + v1 + v2;
-                if (tid == 63) s_soff[kTileThreads] = incl;
-            }
+            scan256_wave0(s_soff, tid, nullptr, 0xffffffffu);
             __syncthreads();
             // phase 3: strips of `strip` kept columns, one per lane
             const uint32_t nst = s_soff[kTileThreads];
@@ -568,6 +601,7 @@ __global__ void __launch_bounds__(kTileThreads)
         // tile-local column x >> lw
         const bool shared_tile = s_shared != 0;
         const int64_t zbase = tk0 >> 5;
+        uint32_t *__restrict__ grid = d.grid;
         for (int32_t x = tid; x < nwords; x += kTileThreads) {
             const uint32_t wv = s_bits[x];
             const int32_t cl = x >> p.lw;
@@ -585,14 +619,16 @@ __global__ void __launch_bounds__(kTileThreads)
 // One workgroup per large tet (its candidate box meets more tiles than the
 // cap): the whole box's columns are spread over the workgroup and ORed into
 // the grid with word atomics.  Runs after the tile kernel.
-__global__ void __launch_bounds__(256)
-    k_large_tets(const int4 *__restrict__ q4, const int4 *__restrict__ tets, GridGeom g,
-                 BinBuffers b, uint32_t *__restrict__ grid, int strict) {
+__global__ void __launch_bounds__(256) k_large_tets(MeshTable T, BinBuffers b, int strict) {
     const uint32_t nbig = b.meta[kMetaBig];
     for (uint32_t e = blockIdx.x; e < nbig; e += gridDim.x) {
-        const uint32_t t = b.big[e];
-        const int4 T = tets[t];
-        const int4 A = q4[T.x], B = q4[T.y], C = q4[T.z], D = q4[T.w];
+        const int64_t t = b.big[e];
+        const int32_t m = T.n == 1 ? 0 : find_mesh(T.tet_pre, T.n, t);
+        const MeshDesc &d = mesh_desc(T, m);
+        const GridGeom g = d.g;
+        const int4 Tt = d.tets[t - d.tet_base];
+        const int4 *q4 = b.q4 + d.vert_base;
+        const int4 A = q4[Tt.x], B = q4[Tt.y], C = q4[Tt.z], D = q4[Tt.w];
         int32_t lo[3], hi[3];
         candidate_box(A, B, C, D, g, lo, hi);
         const double p0[3] = {(double)((2 * lo[0] + 1) * g.half[0]),
@@ -611,7 +647,7 @@ __global__ void __launch_bounds__(256)
             column_span(f, lower, (double)di, (double)dj, nk, nkd, s0, s1);
             if (s0 < s1) {
                 const int64_t col = (int64_t)(lo[0] + di) * g.n[1] + (lo[1] + dj);
-                or_run_global(grid + col * g.words, lo[2] + s0, lo[2] + s1);
+                or_run_global(d.grid + col * g.words, lo[2] + s0, lo[2] + s1);
             }
         }
     }
@@ -623,15 +659,13 @@ __global__ void __launch_bounds__(256)
 // column's span into the grid with word atomics.  The plainest form of the
 // bounding-box scan; kept as an A/B reference for the tile pipeline (the
 // grid must be cleared first).
-__global__ void k_voxelize_per_tet(const int4 *__restrict__ q4, int64_t nv,
-                                   const int4 *__restrict__ tets, int64_t nt, GridGeom g,
-                                   uint32_t *__restrict__ grid, uint32_t *__restrict__ status,
-                                   int strict) {
+__global__ void k_voxelize_per_tet(MeshDesc d, BinBuffers b, int strict) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nt) return;
+    if (t >= d.nt) return;
     int4 V[4];
-    if (!gather_tet(q4, nv, tets, t, status, V)) return;
+    if (!gather_tet(d, b.q4, t, b.status, V)) return;
     int32_t lo[3], hi[3];
+    const GridGeom g = d.g;
     if (!candidate_box(V[0], V[1], V[2], V[3], g, lo, hi)) return;
     const double p0[3] = {(double)((2 * lo[0] + 1) * g.half[0]),
                           (double)((2 * lo[1] + 1) * g.half[1]),
@@ -647,7 +681,7 @@ __global__ void k_voxelize_per_tet(const int4 *__restrict__ q4, int64_t nv,
             column_span(f, lower, (double)di, (double)dj, nk, nkd, s0, s1);
             if (s0 < s1) {
                 const int64_t col = (int64_t)(lo[0] + di) * g.n[1] + (lo[1] + dj);
-                or_run_global(grid + col * g.words, lo[2] + s0, lo[2] + s1);
+                or_run_global(d.grid + col * g.words, lo[2] + s0, lo[2] + s1);
             }
         }
     }
@@ -657,16 +691,13 @@ __global__ void k_voxelize_per_tet(const int4 *__restrict__ q4, int64_t nv,
 
 namespace {
 constexpr int kBlock = 256;
-inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+inline unsigned blocks_for(int64_t n, int block = kBlock) {
+    return (unsigned)((n + block - 1) / block);
+}
 }  // namespace
 
-void launch_ingest_f32(const float *v, int64_t nv, const BoxD &box, int4 *q4, uint32_t *status,
-                       hipStream_t s) {
-    if (nv > 0) k_ingest_f32<<<blocks_for(nv), kBlock, 0, s>>>(v, nv, box, q4, status);
-}
-
-void launch_ingest_q32(const int32_t *q, int64_t nv, int4 *q4, uint32_t *status, hipStream_t s) {
-    if (nv > 0) k_ingest_q32<<<blocks_for(nv), kBlock, 0, s>>>(q, nv, q4, status);
+void launch_ingest(const MeshTable &T, const BinBuffers &b, hipStream_t s) {
+    if (T.nv_total > 0) k_ingest<<<blocks_for(T.nv_total), kBlock, 0, s>>>(T, b);
 }
 
 void launch_snap_only(const float *v, int64_t nv, const BoxD &box, int32_t *q, hipStream_t s) {
@@ -681,47 +712,41 @@ void launch_clear(uint32_t *p, int64_t nwords, hipStream_t s) {
     k_clear<<<(unsigned)want, kBlock, 0, s>>>(p, nwords);
 }
 
-void launch_bin_count(const int4 *q4, int64_t nv, const int4 *tets, int64_t nt, const GridGeom &g,
-                      const TilePlan &p, const BinBuffers &b, hipStream_t s) {
-    if (nt > 0)
-        k_bin<false><<<(unsigned)((nt + kBinThreads - 1) / kBinThreads), kBinThreads, 0, s>>>(
-            q4, nv, tets, nt, g, p, b);
+void launch_set_word(uint32_t *p, uint32_t value, hipStream_t s) {
+    k_set_word<<<1, 1, 0, s>>>(p, value);
 }
 
-void launch_scan_tiles(const TilePlan &p, const BinBuffers &b, hipStream_t s) {
-    k_scan_tiles<<<1, 1024, 0, s>>>(p, b);
+void launch_bin_count(const MeshTable &T, const BinBuffers &b, hipStream_t s) {
+    if (T.nt_total > 0)
+        k_bin<false><<<blocks_for(T.nt_total, kBinThreads), kBinThreads, 0, s>>>(T, b);
 }
 
-void launch_bin_scatter(const int4 *q4, int64_t nv, const int4 *tets, int64_t nt,
-                        const GridGeom &g, const TilePlan &p, const BinBuffers &b, hipStream_t s) {
-    if (nt > 0)
-        k_bin<true><<<(unsigned)((nt + kBinThreads - 1) / kBinThreads), kBinThreads, 0, s>>>(
-            q4, nv, tets, nt, g, p, b);
+void launch_scan_tiles(const MeshTable &T, const BinBuffers &b, hipStream_t s) {
+    k_scan_tiles<<<1, 1024, 0, s>>>(T, b);
 }
 
-void launch_zero_shared_tiles(const GridGeom &g, const TilePlan &p, const BinBuffers &b,
-                              uint32_t *grid, hipStream_t s) {
-    k_zero_shared_tiles<<<(unsigned)p.ntiles, kBlock, 0, s>>>(g, p, b, grid);
+void launch_bin_scatter(const MeshTable &T, const BinBuffers &b, hipStream_t s) {
+    if (T.nt_total > 0)
+        k_bin<true><<<blocks_for(T.nt_total, kBinThreads), kBinThreads, 0, s>>>(T, b);
 }
 
-void launch_tile_voxelize(const int4 *q4, const int4 *tets, const GridGeom &g, const TilePlan &p,
-                          const BinBuffers &b, uint32_t *grid, bool strict, int workgroups,
+void launch_zero_shared_tiles(const MeshTable &T, const BinBuffers &b, hipStream_t s) {
+    if (T.ntiles_total > 0)
+        k_zero_shared_tiles<<<(unsigned)T.ntiles_total, kBlock, 0, s>>>(T, b);
+}
+
+void launch_tile_voxelize(const MeshTable &T, const BinBuffers &b, bool strict, int workgroups,
                           hipStream_t s) {
-    k_tile_voxelize<<<(unsigned)workgroups, kTileThreads, 0, s>>>(q4, tets, g, p, b, grid,
-                                                                   strict ? 1 : 0);
+    k_tile_voxelize<<<(unsigned)workgroups, kTileThreads, 0, s>>>(T, b, strict ? 1 : 0);
 }
 
-void launch_large_tets(const int4 *q4, const int4 *tets, const GridGeom &g, const BinBuffers &b,
-                       uint32_t *grid, bool strict, int workgroups, hipStream_t s) {
-    k_large_tets<<<(unsigned)workgroups, 256, 0, s>>>(q4, tets, g, b, grid, strict ? 1 : 0);
+void launch_large_tets(const MeshTable &T, const BinBuffers &b, bool strict, int workgroups,
+                       hipStream_t s) {
+    k_large_tets<<<(unsigned)workgroups, 256, 0, s>>>(T, b, strict ? 1 : 0);
 }
 
-void launch_voxelize_per_tet(const int4 *q4, int64_t nv, const int4 *tets, int64_t nt,
-                             const GridGeom &g, uint32_t *grid, uint32_t *status, bool strict,
-                             hipStream_t s) {
-    if (nt > 0)
-        k_voxelize_per_tet<<<blocks_for(nt), kBlock, 0, s>>>(q4, nv, tets, nt, g, grid, status,
-                                                             strict ? 1 : 0);
+void launch_voxelize_per_tet(const MeshDesc &d, const BinBuffers &b, bool strict, hipStream_t s) {
+    if (d.nt > 0) k_voxelize_per_tet<<<blocks_for(d.nt), kBlock, 0, s>>>(d, b, strict ? 1 : 0);
 }
 
 int tile_max_words() { return kMaxTileWords; }

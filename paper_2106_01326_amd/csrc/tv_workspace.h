@@ -1,5 +1,5 @@
-// Tile planning and workspace layout of the single-mesh path (byte offsets
-// into the caller's 256-byte aligned workspace).
+// Tile planning and workspace layout (byte offsets into the caller's
+// 256-byte aligned workspace), shared by the single-mesh and batch calls.
 #pragma once
 
 #include <stddef.h>
@@ -10,9 +10,8 @@
 
 namespace tv {
 
-constexpr int32_t kStatusWords = 64;  // per-mesh device status words
-constexpr size_t kStatusOffset = 0;
 constexpr int32_t kMetaWords = 64;
+constexpr int32_t kMinStatusWords = 64;
 constexpr int32_t kPieceCap = 8;
 constexpr int32_t kChunkPieces = 4096;
 constexpr int32_t kStripColumns = 8;
@@ -27,7 +26,9 @@ inline int ilog2(int64_t n) {
 
 // Tiles of at most 32 x 32 columns x 4 words (16 KiB of LDS bitmap), made
 // smaller (down to 8 x 8 columns) while the grid has fewer than
-// `min_tiles` of them, so that small grids still spread over the chip.
+// `min_tiles` of them, so that a lone small grid still spreads over the
+// chip.  (Batches pass min_tiles = 1: their parallelism comes from the
+// number of meshes.)
 inline TilePlan plan_tiles(tv_dims d, int64_t min_tiles) {
     TilePlan p;
     const int W = (d.nz + 31) / 32;
@@ -45,63 +46,78 @@ inline TilePlan plan_tiles(tv_dims d, int64_t min_tiles) {
     p.nty = d.ny >> p.ly;
     p.ntz = W >> p.lw;
     p.ntiles = count();
-    p.chunk = kChunkPieces;
-    p.strip = kStripColumns;
-    p.piece_cap = kPieceCap;
     return p;
 }
 
+// Sizes of one call (a single mesh or a batch).
+struct CallSizes {
+    int64_t meshes;
+    int64_t nv, nt, ntiles;  // totals over the meshes
+};
+
 struct WorkspaceLayout {
-    size_t status;       // kStatusWords uint32
-    size_t meta;         // kMetaWords uint32
+    size_t meta;         // kMetaWords uint32 (fixed at offset 0)
+    size_t status;       // max(kMinStatusWords, meshes) uint32
     size_t tile_count;   // ntiles uint32
     size_t tile_cursor;  // ntiles uint32
-    size_t clear_end;    // [status, clear_end) is zeroed at the start of a call
+    size_t clear_end;    // [0, clear_end) is zeroed at the start of a call
     size_t tile_off;     // ntiles + 1
     size_t chunk_off;    // ntiles + 1
+    size_t descs;        // meshes MeshDesc, then 3 x (meshes + 1) int64 prefix sums
+    size_t descs_bytes;
     size_t q4;           // nv int4 lattice vertices (.w = invalid flag)
-    size_t pieces;       // nt * piece_cap uint32
+    size_t pieces;       // nt * kPieceCap uint32
     size_t big;          // nt uint32
     size_t total;
 };
 
-inline WorkspaceLayout single_layout(int64_t nv, int64_t nt, const TilePlan &p) {
+inline int64_t status_words(int64_t meshes) {
+    return meshes > kMinStatusWords ? meshes : kMinStatusWords;
+}
+
+inline WorkspaceLayout layout(const CallSizes &c) {
     WorkspaceLayout L;
     size_t off = 0;
-    L.status = off;
-    off += sizeof(uint32_t) * kStatusWords;
     L.meta = off;
     off += sizeof(uint32_t) * kMetaWords;
+    L.status = off;
+    off += sizeof(uint32_t) * (size_t)status_words(c.meshes);
     L.tile_count = off;
-    off += 4 * (size_t)p.ntiles;
+    off += 4 * (size_t)c.ntiles;
     L.tile_cursor = off;
-    off += 4 * (size_t)p.ntiles;
+    off += 4 * (size_t)c.ntiles;
     L.clear_end = off;
     off = align256(off);
     L.tile_off = off;
-    off = align256(off + 4 * ((size_t)p.ntiles + 1));
+    off = align256(off + 4 * ((size_t)c.ntiles + 1));
     L.chunk_off = off;
-    off = align256(off + 4 * ((size_t)p.ntiles + 1));
+    off = align256(off + 4 * ((size_t)c.ntiles + 1));
+    L.descs = off;
+    L.descs_bytes = c.meshes > 1 ? sizeof(MeshDesc) * (size_t)c.meshes +
+                                       3 * sizeof(int64_t) * ((size_t)c.meshes + 1)
+                                 : 0;
+    off = align256(off + L.descs_bytes);
     L.q4 = off;
-    off = align256(off + 16 * (size_t)nv);
+    off = align256(off + 16 * (size_t)c.nv);
     L.pieces = off;
-    off = align256(off + 4 * (size_t)nt * (size_t)p.piece_cap);
+    off = align256(off + 4 * (size_t)c.nt * (size_t)kPieceCap);
     L.big = off;
-    off = align256(off + 4 * (size_t)nt);
+    off = align256(off + 4 * (size_t)c.nt);
     L.total = off;
     return L;
 }
 
 inline BinBuffers bin_buffers(uint8_t *ws, const WorkspaceLayout &L) {
     BinBuffers b;
-    b.status = reinterpret_cast<uint32_t *>(ws + L.status);
     b.meta = reinterpret_cast<uint32_t *>(ws + L.meta);
+    b.status = reinterpret_cast<uint32_t *>(ws + L.status);
     b.tile_count = reinterpret_cast<uint32_t *>(ws + L.tile_count);
     b.tile_cursor = reinterpret_cast<uint32_t *>(ws + L.tile_cursor);
     b.tile_off = reinterpret_cast<uint32_t *>(ws + L.tile_off);
     b.chunk_off = reinterpret_cast<uint32_t *>(ws + L.chunk_off);
     b.pieces = reinterpret_cast<uint32_t *>(ws + L.pieces);
     b.big = reinterpret_cast<uint32_t *>(ws + L.big);
+    b.q4 = reinterpret_cast<int4 *>(ws + L.q4);
     return b;
 }
 

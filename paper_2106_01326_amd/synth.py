@@ -323,12 +323,24 @@ def batch_mesh(p) -> Mesh:
     return make_mesh(p["n"], p["delta"], p["grid"], "ellipsoids", p["k"], p["seed"], "f32")
 
 
-def workload_batch(count: int = 1024, seed: int = 3, first: int | None = None):
-    """The uneven batch (1024 meshes by default); ``first`` truncates it."""
+def workload_batch(count: int = 1024, seed: int = 3, first: int | None = None,
+                   workers: int | None = None):
+    """The uneven batch (1024 meshes by default); ``first`` truncates it.
+    Meshes are generated in ``workers`` processes (each mesh is seeded on its
+    own, so the result does not depend on the worker count)."""
     ps = batch_params(count, seed)
     if first is not None:
         ps = ps[:first]
-    return [batch_mesh(p) for p in ps]
+    if workers is None:
+        import os
+
+        workers = min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else 1)
+    if workers <= 1 or len(ps) < 8:
+        return [batch_mesh(p) for p in ps]
+    import multiprocessing as mp
+
+    with mp.get_context("fork").Pool(workers) as pool:
+        return pool.map(batch_mesh, ps, chunksize=4)
 
 
 def medium_shape_fp32(seed) -> Mesh:

@@ -72,3 +72,20 @@ def test_binding_fails_loudly_without_library(monkeypatch):
     monkeypatch.setattr(tv, "LIB_PATH", "/nonexistent/libtetvox.so")
     with pytest.raises(RuntimeError, match="missing"):
         tv.load_library()
+
+
+def test_batch_host_errors_name_the_mesh(lib):
+    P = ctypes.c_void_p
+    good = tv.MeshC(256, tv.VERTS_F32, 4, 256, 1, tv.Dims(8, 8, 8),
+                    tv.BBox((ctypes.c_float * 3)(0, 0, 0), (ctypes.c_float * 3)(1, 1, 1)), 256)
+    bad = tv.MeshC(256, tv.VERTS_F32, 4, 256, 1, tv.Dims(8, 6, 8),
+                   tv.BBox((ctypes.c_float * 3)(0, 0, 0), (ctypes.c_float * 3)(1, 1, 1)), 256)
+    arr = (tv.MeshC * 3)(good, good, bad)
+    assert lib.tv_batch_workspace_bytes(ctypes.cast(arr, P), 3, 0) == 0
+    assert lib.tv_voxelize_batch(ctypes.cast(arr, P), 3, P(256), 1 << 30, None, 0) == tv.TV_ERR_UNSUPPORTED_DIMS
+    assert b"mesh 2" in lib.tv_last_error()
+    arr2 = (tv.MeshC * 2)(good, good)
+    need = lib.tv_batch_workspace_bytes(ctypes.cast(arr2, P), 2, 0)
+    assert need > 0
+    assert lib.tv_voxelize_batch(ctypes.cast(arr2, P), 2, P(256), need - 256, None, 0) == tv.TV_ERR_WORKSPACE
+    assert lib.tv_voxelize_batch(ctypes.cast(arr2, P), 0, P(256), need, None, 0) == tv.TV_ERR_INVALID_ARG
