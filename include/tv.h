@@ -65,6 +65,9 @@ typedef int32_t tv_status;
 #define TV_ERR_RANGE (-4)            /* (device) NaN or coordinate off the lattice range */
 #define TV_ERR_WORKSPACE (-5)        /* workspace null, misaligned or too small */
 #define TV_ERR_HIP (-7)              /* a HIP runtime call failed */
+#define TV_ERR_TOO_LARGE (-8)        /* request larger than the server's memory */
+#define TV_ERR_TIMEOUT (-9)          /* wait timed out */
+#define TV_ERR_NOT_FOUND (-10)       /* unknown ticket, or result asked before completion */
 
 #define TV_Q_MIN (-16384)        /* lattice range: [-2^14, 2^16 + 2^14] per axis */
 #define TV_Q_MAX (65536 + 16384)
@@ -169,6 +172,84 @@ tv_status tv_fetch_status(const void *ws, int32_t mesh_index, void *stream);
 tv_status tv_profile_enable(int32_t on);
 tv_status tv_profile_read(double *ms_out, int32_t max_stages, int32_t *n_stages, int64_t *n_calls);
 const char *tv_profile_stage_name(int32_t stage);
+
+/*
+ * Serving: a continuous-batching server for voxelization requests (the
+ * paper's observation that for small models transfer and allocation cost
+ * more than the voxelization itself, Section 3 "Parallelization" and
+ * Table 1, is why requests are batched and memory is kept allocated).
+ *
+ *   - tv_server_create allocates, once, a device arena (inputs, grids and
+ *     wave workspaces live in it) and a pinned host staging area, creates
+ *     `streams` compute streams and starts a scheduler and a completion
+ *     thread on the current device.
+ *   - tv_server_submit queues a request (host or device inputs, see flags);
+ *     the scheduler admits queued requests in FIFO order while their memory
+ *     footprint (inputs + grid + workspace share) fits in the arena and a
+ *     stream is free, groups them into a wave (one batched launch sequence,
+ *     tv_voxelize_batch semantics) and launches it; requests that arrive
+ *     while other waves run are admitted into the next wave as soon as a
+ *     stream and memory free up, so waves overlap on the device.
+ *   - A request's grid stays in device memory after completion until
+ *     tv_server_release; tv_server_result gives its device address, and its
+ *     latency (completion - submission, host steady clock).
+ *   - All calls are thread-safe; results equal tv_voxelize's bit for bit.
+ */
+typedef struct tv_server tv_server;
+
+#define TV_REQ_HOST_INPUTS 0u   /* verts/tets in pageable host memory: staged through pinned memory */
+#define TV_REQ_PINNED_INPUTS 4u /* verts/tets in pinned host memory: copied directly */
+#define TV_REQ_DEVICE_INPUTS 8u /* verts/tets already in device memory: not copied */
+
+typedef struct {
+    const void *verts;     /* [nv][3] float32 world or int32 lattice (vert_format) */
+    uint32_t vert_format;  /* TV_VERTS_F32 or TV_VERTS_Q32 */
+    int64_t nv;
+    const int32_t *tets;   /* [nt][4] int32 */
+    int64_t nt;
+    tv_dims dims;
+    tv_bbox bbox;
+    uint32_t flags;        /* TV_TIE_STRICT | one TV_REQ_*_INPUTS; inputs must stay valid
+                              until the request is done */
+} tv_request;
+
+typedef struct {
+    size_t device_bytes;      /* device arena */
+    size_t pinned_bytes;      /* pinned host staging (0: pageable inputs are refused) */
+    int32_t streams;          /* waves in flight at once (>= 1) */
+    int32_t max_wave_meshes;  /* meshes per wave (>= 1) */
+} tv_server_config;
+
+typedef struct {
+    int64_t submitted, completed, released, rejected;
+    int64_t waves;            /* waves launched */
+    int64_t queued;           /* requests waiting for admission */
+    int64_t running;          /* requests in waves on the device */
+    int64_t inflight_waves;
+    size_t device_in_use, device_peak, pinned_in_use;
+} tv_server_stats;
+
+#define TV_REQ_QUEUED 0
+#define TV_REQ_RUNNING 1
+#define TV_REQ_DONE 2
+
+tv_status tv_server_create(const tv_server_config *cfg, tv_server **out);
+/* Queues a request; TV_ERR_TOO_LARGE when it could never fit. */
+tv_status tv_server_submit(tv_server *s, const tv_request *req, int64_t *ticket);
+tv_status tv_server_poll(tv_server *s, int64_t ticket, int32_t *state);
+/* Blocks until the request is done (TV_ERR_TIMEOUT after timeout_s > 0). */
+tv_status tv_server_wait(tv_server *s, int64_t ticket, double timeout_s);
+/* Done request: device grid address and word count, the request's data
+ * status (TV_OK / TV_ERR_INDEX / TV_ERR_RANGE) and latency in seconds. */
+tv_status tv_server_result(tv_server *s, int64_t ticket, const uint32_t **grid, size_t *words,
+                           tv_status *data_status, double *latency_s);
+/* Copies a done request's grid to `dst` (host or device memory; blocking). */
+tv_status tv_server_copy_grid(tv_server *s, int64_t ticket, void *dst, size_t words);
+/* Frees a done request's grid. */
+tv_status tv_server_release(tv_server *s, int64_t ticket);
+tv_status tv_server_get_stats(tv_server *s, tv_server_stats *out);
+/* Waits for in-flight waves, stops the threads and frees everything. */
+tv_status tv_server_destroy(tv_server *s);
 
 /* Human-readable name of a status code (static storage). */
 const char *tv_status_string(tv_status s);

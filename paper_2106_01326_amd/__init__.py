@@ -25,6 +25,9 @@ TV_ERR_INDEX = -3
 TV_ERR_RANGE = -4
 TV_ERR_WORKSPACE = -5
 TV_ERR_HIP = -7
+TV_ERR_TOO_LARGE = -8
+TV_ERR_TIMEOUT = -9
+TV_ERR_NOT_FOUND = -10
 
 TIE_HALF_OPEN = 0
 TIE_STRICT = 1
@@ -37,7 +40,14 @@ VERTS_Q32 = 1
 EXPORTED = ("tv_grid_words", "tv_workspace_bytes", "tv_voxelize", "tv_voxelize_q", "tv_snap",
             "tv_batch_workspace_bytes", "tv_voxelize_batch",
             "tv_fetch_status", "tv_status_string", "tv_last_error", "tv_profile_enable",
-            "tv_profile_read", "tv_profile_stage_name")
+            "tv_profile_read", "tv_profile_stage_name", "tv_server_create", "tv_server_submit",
+            "tv_server_poll", "tv_server_wait", "tv_server_result", "tv_server_copy_grid",
+            "tv_server_release", "tv_server_get_stats", "tv_server_destroy")
+
+REQ_HOST_INPUTS = 0
+REQ_PINNED_INPUTS = 4
+REQ_DEVICE_INPUTS = 8
+REQ_DONE = 2
 
 
 class Dims(ctypes.Structure):
@@ -52,6 +62,25 @@ class MeshC(ctypes.Structure):
     _fields_ = [("verts", ctypes.c_void_p), ("vert_format", ctypes.c_uint32), ("nv", ctypes.c_int64),
                 ("tets", ctypes.c_void_p), ("nt", ctypes.c_int64), ("dims", Dims), ("bbox", BBox),
                 ("grid", ctypes.c_void_p)]
+
+
+class RequestC(ctypes.Structure):
+    _fields_ = [("verts", ctypes.c_void_p), ("vert_format", ctypes.c_uint32), ("nv", ctypes.c_int64),
+                ("tets", ctypes.c_void_p), ("nt", ctypes.c_int64), ("dims", Dims), ("bbox", BBox),
+                ("flags", ctypes.c_uint32)]
+
+
+class ServerConfigC(ctypes.Structure):
+    _fields_ = [("device_bytes", ctypes.c_size_t), ("pinned_bytes", ctypes.c_size_t),
+                ("streams", ctypes.c_int32), ("max_wave_meshes", ctypes.c_int32)]
+
+
+class ServerStatsC(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("released", ctypes.c_int64),
+                ("rejected", ctypes.c_int64), ("waves", ctypes.c_int64), ("queued", ctypes.c_int64),
+                ("running", ctypes.c_int64), ("inflight_waves", ctypes.c_int64),
+                ("device_in_use", ctypes.c_size_t), ("device_peak", ctypes.c_size_t),
+                ("pinned_in_use", ctypes.c_size_t)]
 
 
 class TVError(RuntimeError):
@@ -75,6 +104,12 @@ def load_library():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                            "`python -m paper_2106_01326_amd.build` (no CPU fallback exists)")
+    # torch ships its own HIP runtime and loads it under a file name that the
+    # loader does not match against an already loaded /opt/rocm runtime;
+    # loading torch first makes this library bind to torch's runtime, so the
+    # process has exactly one.
+    import torch  # noqa: F401
+
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.c_void_p
     i64 = ctypes.c_int64
@@ -100,6 +135,24 @@ def load_library():
     lib.tv_status_string.restype = ctypes.c_char_p
     lib.tv_last_error.argtypes = []
     lib.tv_last_error.restype = ctypes.c_char_p
+    lib.tv_server_create.argtypes = [P, P]
+    lib.tv_server_create.restype = st
+    lib.tv_server_submit.argtypes = [P, P, P]
+    lib.tv_server_submit.restype = st
+    lib.tv_server_poll.argtypes = [P, i64, P]
+    lib.tv_server_poll.restype = st
+    lib.tv_server_wait.argtypes = [P, i64, ctypes.c_double]
+    lib.tv_server_wait.restype = st
+    lib.tv_server_result.argtypes = [P, i64, P, P, P, P]
+    lib.tv_server_result.restype = st
+    lib.tv_server_copy_grid.argtypes = [P, i64, P, ctypes.c_size_t]
+    lib.tv_server_copy_grid.restype = st
+    lib.tv_server_release.argtypes = [P, i64]
+    lib.tv_server_release.restype = st
+    lib.tv_server_get_stats.argtypes = [P, P]
+    lib.tv_server_get_stats.restype = st
+    lib.tv_server_destroy.argtypes = [P]
+    lib.tv_server_destroy.restype = st
     lib.tv_profile_enable.argtypes = [ctypes.c_int32]
     lib.tv_profile_enable.restype = st
     lib.tv_profile_read.argtypes = [P, ctypes.c_int32, P, P]
@@ -304,3 +357,96 @@ def voxelize_batch(items, strict=False, per_tet=False, stream=None):
     (verts, tets, dims, bbox, qverts).  Returns (grids, Batch)."""
     b = Batch(items)
     return b.run(strict=strict, per_tet=per_tet, stream=stream), b
+
+
+class Server:
+    """Continuous-batching voxelization server (tv_server_* in the C ABI).
+
+    Requests carry numpy arrays (pageable or pinned host memory) or device
+    tensors; the caller keeps them alive until the request is done.  Grids
+    stay on the device until ``release``."""
+
+    def __init__(self, device_bytes=8 << 30, pinned_bytes=1 << 30, streams=2, max_wave_meshes=1024):
+        lib = load_library()
+        cfg = ServerConfigC(int(device_bytes), int(pinned_bytes), int(streams), int(max_wave_meshes))
+        h = ctypes.c_void_p()
+        _check(lib.tv_server_create(ctypes.cast(ctypes.pointer(cfg), ctypes.c_void_p),
+                                    ctypes.cast(ctypes.pointer(h), ctypes.c_void_p)))
+        self._h = h
+        self._keep = {}
+
+    def submit(self, verts, tets, dims, bbox=None, *, qverts=False, strict=False, inputs="host"):
+        """Queue one request; returns its ticket.  ``inputs`` is "host"
+        (numpy, staged through pinned memory), "pinned" (pinned torch CPU
+        tensors, copied directly) or "device" (device tensors)."""
+        lib = load_library()
+        if inputs == "device" or inputs == "pinned":
+            vptr, nv = verts.data_ptr(), int(verts.shape[0])
+            tptr, nt = tets.data_ptr(), int(tets.shape[0])
+        else:
+            import numpy as np
+
+            verts = np.ascontiguousarray(verts, dtype=np.int32 if qverts else np.float32)
+            tets = np.ascontiguousarray(tets, dtype=np.int32)
+            vptr, nv = verts.ctypes.data, int(verts.shape[0])
+            tptr, nt = tets.ctypes.data, int(tets.shape[0])
+        flags = {"host": REQ_HOST_INPUTS, "pinned": REQ_PINNED_INPUTS, "device": REQ_DEVICE_INPUTS}[inputs]
+        if strict:
+            flags |= TIE_STRICT
+        if bbox is None:
+            bbox = ((0.0, 0.0, 0.0), (1.0, 1.0, 1.0))
+        req = RequestC(vptr, VERTS_Q32 if qverts else VERTS_F32, nv, tptr, nt, _dims(dims), _bbox(bbox), flags)
+        t = ctypes.c_int64()
+        _check(lib.tv_server_submit(self._h, ctypes.cast(ctypes.pointer(req), ctypes.c_void_p),
+                                    ctypes.cast(ctypes.pointer(t), ctypes.c_void_p)))
+        self._keep[t.value] = (verts, tets)
+        return t.value
+
+    def poll(self, ticket):
+        st = ctypes.c_int32()
+        _check(load_library().tv_server_poll(self._h, ticket, ctypes.cast(ctypes.pointer(st), ctypes.c_void_p)))
+        return st.value
+
+    def wait(self, ticket, timeout=0.0):
+        _check(load_library().tv_server_wait(self._h, ticket, float(timeout)))
+
+    def result(self, ticket):
+        """(device grid address, words, data status, latency seconds)."""
+        g = ctypes.c_void_p()
+        n = ctypes.c_size_t()
+        ds = ctypes.c_int32()
+        lat = ctypes.c_double()
+        P = ctypes.c_void_p
+        _check(load_library().tv_server_result(self._h, ticket, ctypes.cast(ctypes.pointer(g), P),
+                                               ctypes.cast(ctypes.pointer(n), P),
+                                               ctypes.cast(ctypes.pointer(ds), P),
+                                               ctypes.cast(ctypes.pointer(lat), P)))
+        return g.value, n.value, ds.value, lat.value
+
+    def copy_grid(self, ticket, out):
+        """Copy a done request's grid into ``out`` (numpy uint32 or a torch
+        int32 tensor, host or device)."""
+        ptr = out.ctypes.data if hasattr(out, "ctypes") else out.data_ptr()
+        _check(load_library().tv_server_copy_grid(self._h, ticket, ctypes.c_void_p(ptr), int(out.size if hasattr(out, "ctypes") else out.numel())))
+        return out
+
+    def release(self, ticket):
+        _check(load_library().tv_server_release(self._h, ticket))
+        self._keep.pop(ticket, None)
+
+    def stats(self):
+        st = ServerStatsC()
+        _check(load_library().tv_server_get_stats(self._h, ctypes.cast(ctypes.pointer(st), ctypes.c_void_p)))
+        return {k: getattr(st, k) for k, _ in ServerStatsC._fields_}
+
+    def close(self):
+        if self._h:
+            _check(load_library().tv_server_destroy(self._h))
+            self._h = None
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

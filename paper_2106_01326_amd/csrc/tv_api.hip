@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "tv.h"
+#include "tv_internal.h"
 #include "tv_kernels.h"
 #include "tv_profile.h"
 #include "tv_workspace.h"
@@ -70,7 +71,7 @@ constexpr uint32_t kKnownFlags = TV_TIE_STRICT | TV_PATH_PER_TET;
 constexpr int64_t kMaxTets = (int64_t)1 << 28;  // piece slots stay below 2^32
 
 // Host-visible checks of one mesh; `which` prefixes messages of batch entries.
-tv_status check_mesh(const void *verts, uint32_t fmt, int64_t nv, const int32_t *tets, int64_t nt,
+tv_status check_mesh_impl(const void *verts, uint32_t fmt, int64_t nv, const int32_t *tets, int64_t nt,
                      tv_dims dims, const tv_bbox *bbox, const uint32_t *grid, const char *which) {
     if (!pow2_dim(dims.nx) || !pow2_dim(dims.ny) || !pow2_dim(dims.nz))
         return fail(TV_ERR_UNSUPPORTED_DIMS,
@@ -95,7 +96,7 @@ tv_status check_mesh(const void *verts, uint32_t fmt, int64_t nv, const int32_t 
     return TV_OK;
 }
 
-tv::MeshDesc make_desc(const void *verts, uint32_t fmt, int64_t nv, const int32_t *tets,
+tv::MeshDesc make_desc_impl(const void *verts, uint32_t fmt, int64_t nv, const int32_t *tets,
                        int64_t nt, tv_dims dims, const tv_bbox *bbox, uint32_t *grid,
                        int64_t min_tiles) {
     tv::MeshDesc d;
@@ -118,7 +119,7 @@ tv::MeshDesc make_desc(const void *verts, uint32_t fmt, int64_t nv, const int32_
 }
 
 // Fills the bases of the descriptors and the call totals.
-tv::CallSizes assign_bases(std::vector<tv::MeshDesc> &descs) {
+tv::CallSizes assign_bases_impl(std::vector<tv::MeshDesc> &descs) {
     tv::CallSizes c = {(int64_t)descs.size(), 0, 0, 0};
     for (size_t i = 0; i < descs.size(); ++i) {
         tv::MeshDesc &d = descs[i];
@@ -134,7 +135,7 @@ tv::CallSizes assign_bases(std::vector<tv::MeshDesc> &descs) {
 }
 
 // The launch sequence of a call whose descriptors are final.
-tv_status run(std::vector<tv::MeshDesc> &descs, const tv::CallSizes &c, uint8_t *ws, hipStream_t s,
+tv_status run_impl(std::vector<tv::MeshDesc> &descs, const tv::CallSizes &c, uint8_t *ws, hipStream_t s,
               uint32_t flags) {
     const tv::WorkspaceLayout L = tv::layout(c);
     const tv::BinBuffers b = tv::bin_buffers(ws, L);
@@ -222,13 +223,13 @@ tv_status check_ws(void *ws, size_t ws_bytes, size_t need, uint32_t flags) {
 tv_status voxelize_one(const void *verts, uint32_t fmt, int64_t nv, const int32_t *tets, int64_t nt,
                        tv_dims dims, const tv_bbox *bbox, uint32_t *grid, void *ws, size_t ws_bytes,
                        void *stream, uint32_t flags) {
-    tv_status st = check_mesh(verts, fmt, nv, tets, nt, dims, bbox, grid, "");
+    tv_status st = check_mesh_impl(verts, fmt, nv, tets, nt, dims, bbox, grid, "");
     if (st) return st;
     if ((st = check_ws(ws, ws_bytes, tv_workspace_bytes(nv, nt, dims, flags), flags))) return st;
     std::vector<tv::MeshDesc> descs(
-        1, make_desc(verts, fmt, nv, tets, nt, dims, bbox, grid, kMinTilesSingle));
-    const tv::CallSizes c = assign_bases(descs);
-    return run(descs, c, static_cast<uint8_t *>(ws), reinterpret_cast<hipStream_t>(stream), flags);
+        1, make_desc_impl(verts, fmt, nv, tets, nt, dims, bbox, grid, kMinTilesSingle));
+    const tv::CallSizes c = assign_bases_impl(descs);
+    return run_impl(descs, c, static_cast<uint8_t *>(ws), reinterpret_cast<hipStream_t>(stream), flags);
 }
 
 bool batch_descs(const tv_mesh *meshes, int32_t n, std::vector<tv::MeshDesc> &descs,
@@ -239,9 +240,9 @@ bool batch_descs(const tv_mesh *meshes, int32_t n, std::vector<tv::MeshDesc> &de
     for (int32_t i = 0; i < n; ++i) {
         const tv_mesh &m = meshes[i];
         snprintf(which, sizeof which, "mesh %d: ", i);
-        st = check_mesh(m.verts, m.vert_format, m.nv, m.tets, m.nt, m.dims, &m.bbox, m.grid, which);
+        st = check_mesh_impl(m.verts, m.vert_format, m.nv, m.tets, m.nt, m.dims, &m.bbox, m.grid, which);
         if (st) return false;
-        descs.push_back(make_desc(m.verts, m.vert_format, m.nv, m.tets, m.nt, m.dims, &m.bbox,
+        descs.push_back(make_desc_impl(m.verts, m.vert_format, m.nv, m.tets, m.nt, m.dims, &m.bbox,
                                   m.grid, kMinTilesBatch));
     }
     st = TV_OK;
@@ -249,6 +250,35 @@ bool batch_descs(const tv_mesh *meshes, int32_t n, std::vector<tv::MeshDesc> &de
 }
 
 }  // namespace
+
+namespace tv {
+
+tv_status check_mesh(const void *verts, uint32_t fmt, int64_t nv, const int32_t *tets, int64_t nt,
+                     tv_dims dims, const tv_bbox *bbox, const uint32_t *grid, const char *which) {
+    return check_mesh_impl(verts, fmt, nv, tets, nt, dims, bbox, grid, which);
+}
+
+MeshDesc make_batch_desc(const void *verts, uint32_t fmt, int64_t nv, const int32_t *tets,
+                         int64_t nt, tv_dims dims, const tv_bbox *bbox, uint32_t *grid) {
+    return make_desc_impl(verts, fmt, nv, tets, nt, dims, bbox, grid, kMinTilesBatch);
+}
+
+CallSizes assign_bases(std::vector<MeshDesc> &descs) { return assign_bases_impl(descs); }
+
+tv_status run_meshes(std::vector<MeshDesc> &descs, const CallSizes &c, uint8_t *ws, hipStream_t s,
+                     uint32_t flags) {
+    return run_impl(descs, c, ws, s, flags);
+}
+
+tv_status set_error(tv_status code, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_last_error, sizeof g_last_error, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+}  // namespace tv
 
 extern "C" {
 
@@ -284,7 +314,7 @@ size_t tv_batch_workspace_bytes(const tv_mesh *meshes, int32_t n, uint32_t flags
     std::vector<tv::MeshDesc> descs;
     tv_status st;
     if (!batch_descs(meshes, n, descs, st)) return 0;
-    return tv::layout(assign_bases(descs)).total;
+    return tv::layout(assign_bases_impl(descs)).total;
 }
 
 tv_status tv_voxelize_batch(const tv_mesh *meshes, int32_t n, void *ws, size_t ws_bytes,
@@ -293,10 +323,10 @@ tv_status tv_voxelize_batch(const tv_mesh *meshes, int32_t n, void *ws, size_t w
     std::vector<tv::MeshDesc> descs;
     tv_status st;
     if (!batch_descs(meshes, n, descs, st)) return st;
-    const tv::CallSizes c = assign_bases(descs);
+    const tv::CallSizes c = assign_bases_impl(descs);
     if (c.nt > kMaxTets) return fail(TV_ERR_INVALID_ARG, "batch has more than 2^28 tets");
     if ((st = check_ws(ws, ws_bytes, tv::layout(c).total, flags))) return st;
-    return run(descs, c, static_cast<uint8_t *>(ws), reinterpret_cast<hipStream_t>(stream), flags);
+    return run_impl(descs, c, static_cast<uint8_t *>(ws), reinterpret_cast<hipStream_t>(stream), flags);
 }
 
 tv_status tv_snap(const float *verts, int64_t nv, tv_bbox bbox, int32_t *q_out, void *stream) {
