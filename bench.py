@@ -60,8 +60,8 @@ def make_workload(name):
 
 
 def workload_config(name, m):
-    return {"workload": {"large": "large single mesh (config 2)", "medium": "medium single mesh (config 1)",
-                         "small": "small single mesh (config 0)"}[name],
+    return {"workload": {"large": "large single mesh, 1024^3 grid", "medium": "medium single mesh, 256^3 grid",
+                         "small": "small single mesh, 32^3 grid"}[name],
             "cubes_per_axis": m.meta["n"], "jitter": m.meta["delta"], "keep": m.meta["keep"],
             "ellipsoids": m.meta["k"], "grid": list(m.dims), "vert_format": m.fmt,
             "tets": m.nt, "verts": m.nv, "tets_before_keep": m.meta["tets_before_keep"], "seed_index": True}
@@ -113,18 +113,20 @@ def cpu_baseline(m, gpu_words_fn, target_s=12.0):
     cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     cores = max(1, min(cores, 16))
     q = oracle.snap(m.verts, *m.bbox) if m.verts is not None else m.qverts
-    probe = min(m.nt, 20000)
-    t0 = time.perf_counter()
-    oracle.voxelize_q(q, m.tets[:probe], m.dims, threads=cores)
-    rate = probe / max(time.perf_counter() - t0, 1e-6)
-    n = int(min(m.nt, max(probe, rate * target_s)))
-    sample = m.tets[:n]
-    t0 = time.perf_counter()
-    if m.verts is not None:
-        want = oracle.voxelize_q(oracle.snap(m.verts, *m.bbox), sample, m.dims, threads=cores)
-    else:
-        want = oracle.voxelize_q(q, sample, m.dims, threads=cores)
-    dt = time.perf_counter() - t0
+    # grow the sample until one run takes about target_s: a short probe
+    # underestimates the rate (grid clearing and thread start-up dominate it)
+    n = min(m.nt, 20000)
+    while True:
+        sample = m.tets[:n]
+        t0 = time.perf_counter()
+        if m.verts is not None:
+            want = oracle.voxelize_q(oracle.snap(m.verts, *m.bbox), sample, m.dims, threads=cores)
+        else:
+            want = oracle.voxelize_q(q, sample, m.dims, threads=cores)
+        dt = time.perf_counter() - t0
+        if dt >= 0.5 * target_s or n == m.nt:
+            break
+        n = int(min(m.nt, n * min(16.0, max(2.0, 0.9 * target_s / max(dt, 1e-6)))))
     got = gpu_words_fn(sample)
     exact = bool(np.array_equal(got, want))
     return {"value": n / dt, "unit": "tets/s", "cores": cores, "kind": "oracle",
@@ -192,7 +194,7 @@ def bench_batch(args, torch, tv):
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_batch,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
            "data": "synthetic (seeded jittered Kuhn meshes)",
-           "config": {"workload": "uneven batch (config 3)", "meshes": len(meshes), "tets": nt,
+           "config": {"workload": "uneven batch of small meshes", "meshes": len(meshes), "tets": nt,
                       "grids": "32^3 or 64^3", "vert_format": "f32"},
            "tets_per_s": nt / (ms_batch * 1e-3),
            "per_mesh_loop": {"meshes_per_s": len(meshes) / (ms_loop * 1e-3), "ms_per_pass": ms_loop,
@@ -287,7 +289,7 @@ def bench_serving(args, torch, tv):
            "n_gpus": 1, "steps": args.requests, "warmup": 64, "ms_per_step": top["mean_ms"],
            "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
            "data": "synthetic (seeded jittered Kuhn meshes)",
-           "config": {"workload": "serving stream (config 4)", "mix": "90% batch distribution, 10% medium shape",
+           "config": {"workload": "Poisson request stream", "mix": "90% batch distribution, 10% medium shape",
                       "pool": "512 + 32 meshes", "inputs": "pinned host memory", "streams": 2},
            "serving": res, "server_stats": {k: int(v) for k, v in st.items()}, "cpu_baseline": None}
     print(json.dumps(out), flush=True)
@@ -326,6 +328,9 @@ def main():
     ap.add_argument("--batch-meshes", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="before the workload, run one plain device copy of this many MiB so "
+                         "that a hardware-counter run can scale its byte counters")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -340,6 +345,15 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("no GPU visible")
     tv.load_library()
+    if args.copy_calibration_mib > 0:
+        nbytes = args.copy_calibration_mib << 20
+        src = torch.full((nbytes,), 7, dtype=torch.uint8, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {nbytes} bytes read, {nbytes} bytes written")
+        del src, dst
     if args.workload == "batch":
         return bench_batch(args, torch, tv)
     if args.workload == "serving":

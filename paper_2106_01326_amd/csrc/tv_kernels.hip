@@ -42,6 +42,26 @@ __device__ __forceinline__ const MeshDesc &mesh_desc(const MeshTable &T, int32_t
     return T.n == 1 ? T.one : T.descs[m];
 }
 
+// Mesh of global index x for the threads of one workgroup whose indices are
+// [first, last]: two threads bracket the workgroup's meshes once, then each
+// thread searches only inside the bracket (usually a single mesh).  Must be
+// called by every thread of the workgroup.
+__device__ __forceinline__ int32_t find_mesh_block(const MeshTable &T, const int64_t *pre,
+                                                   int64_t first, int64_t last, int64_t x,
+                                                   int32_t *s_bracket) {
+    if (T.n == 1) return 0;
+    if (threadIdx.x == 0) s_bracket[0] = find_mesh(pre, T.n, first);
+    if (threadIdx.x == 1) s_bracket[1] = find_mesh(pre, T.n, last);
+    __syncthreads();
+    int32_t lo = s_bracket[0], hi = s_bracket[1] + 1;  // pre[lo] <= x < pre[hi]
+    while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (pre[mid] <= x) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
 // ----------------------------------------------------------------- ingest
 
 // fp32 world coordinate -> lattice coordinate, per the snap contract:
@@ -63,9 +83,12 @@ __device__ __forceinline__ bool snap_coord(float v, double lo, double ext, int32
 // .w lane marks a vertex that is NaN or off the lattice range (such vertices
 // void their tets and raise the mesh's status).
 __global__ void k_ingest(MeshTable T, BinBuffers b) {
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ int32_t s_bracket[2];
+    const int64_t first = (int64_t)blockIdx.x * blockDim.x;
+    const int64_t last = min(first + (int64_t)blockDim.x, T.nv_total) - 1;
+    const int64_t v = first + threadIdx.x;
+    const int32_t m = find_mesh_block(T, T.vert_pre, first, last, min(v, last), s_bracket);
     if (v >= T.nv_total) return;
-    const int32_t m = T.n == 1 ? 0 : find_mesh(T.vert_pre, T.n, v);
     const MeshDesc &d = mesh_desc(T, m);
     const int64_t i = v - d.vert_base;
     int32_t q[3];
@@ -185,12 +208,12 @@ __device__ __forceinline__ int32_t tet_pieces(const MeshDesc &d, const int4 *__r
 // which mostly share tiles, thus cost one global atomic per workgroup and
 // tile instead of one per piece.
 constexpr int kBinThreads = 256;
-constexpr int kHashSlots = 4096;  // >= 2 * kBinThreads * kPieceCapMax: load <= 1/2
+constexpr int kHashSlots = 2048;  // >= kBinThreads * kPieceCapMax: every probe ends
 constexpr int kPieceCapMax = 8;
 constexpr uint32_t kEmptyKey = 0xffffffffu;
 
 __device__ __forceinline__ uint32_t hash_insert(uint32_t *keys, uint32_t key) {
-    uint32_t h = (key * 2654435761u) >> (32 - 12);
+    uint32_t h = (key * 2654435761u) >> (32 - 11);
     for (;;) {
         const uint32_t prev = atomicCAS(keys + h, kEmptyKey, key);
         if (prev == kEmptyKey || prev == key) return h;
@@ -203,16 +226,19 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(MeshTable T, BinBuffers b) 
     __shared__ uint32_t s_key[kHashSlots];
     __shared__ uint32_t s_cnt[kHashSlots];  // count, then (pass 2) global slot base
     __shared__ uint32_t s_ref[kBinThreads * kPieceCapMax];  // slot << 16 | rank
+    __shared__ int32_t s_bracket[2];
     const int tid = threadIdx.x;
     for (int i = tid; i < kHashSlots; i += kBinThreads) {
         s_key[i] = kEmptyKey;
         s_cnt[i] = 0u;
     }
     __syncthreads();
-    const int64_t t = (int64_t)blockIdx.x * kBinThreads + tid;
+    const int64_t first = (int64_t)blockIdx.x * kBinThreads;
+    const int64_t last = min(first + (int64_t)kBinThreads, T.nt_total) - 1;
+    const int64_t t = first + tid;
+    const int32_t m = find_mesh_block(T, T.tet_pre, first, last, min(t, last), s_bracket);
     int32_t np = 0;
     if (t < T.nt_total) {
-        const int32_t m = T.n == 1 ? 0 : find_mesh(T.tet_pre, T.n, t);
         const MeshDesc &d = mesh_desc(T, m);
         TileRange r = {0, -1, 0, -1, 0, -1};
         // status flags are raised by the counting pass only
@@ -355,30 +381,49 @@ __device__ __forceinline__ void column_span(const Face f[4], uint32_t lower, dou
     }
 }
 
+// Vertex projections of a tet for the per-row culling below: x and y of the
+// 4 vertices and, per vertex pair, 1/(x_a - x_c) (0 for a pair at equal x).
+struct Silhouette {
+    double vx[4], vy[4], inv[6];
+};
+
+__device__ __forceinline__ void make_silhouette(const int4 V[4], Silhouette &s) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        s.vx[a] = (double)V[a].x;
+        s.vy[a] = (double)V[a].y;
+    }
+    int k = 0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = a + 1; c < 4; ++c, ++k)
+            s.inv[k] = s.vx[a] != s.vx[c] ? 1.0 / (s.vx[a] - s.vx[c]) : 0.0;
+}
+
 // Columns of row x = cx (lattice) that the tet's projection onto the xy
 // plane can reach: the cross-section of the tet's vertex hull with the plane
 // x = cx spans y in [ylo, yhi], the extremes over the 6 vertex pairs whose
-// segment meets the plane.  Evaluated in double with a one-unit margin on
-// each side (conservative); the exact span test decides every column kept.
-// Returns the inclusive index range [j0, j1] (empty when j0 > j1).
-__device__ __forceinline__ void row_columns(const double vx[4], const double vy[4], double cx,
-                                            const GridGeom &g, int32_t &j0, int32_t &j1) {
+// segment meets the plane (both ends for a pair lying in the plane).
+// Evaluated in double with a one-unit margin on each side (conservative);
+// the exact span test decides every column kept.  Returns the inclusive
+// index range [j0, j1] (empty when j0 > j1).
+__device__ __forceinline__ void row_columns(const Silhouette &sh, double cx, const GridGeom &g,
+                                            int32_t &j0, int32_t &j1) {
     double ylo = 1e300, yhi = -1e300;
+    int k = 0;
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
 #pragma unroll
-        for (int c = a + 1; c < 4; ++c) {
-            const double da = vx[a] - cx, dc = vx[c] - cx;
-            if (da * dc <= 0.0) {  // the segment meets the plane (or lies in it)
-                if (vx[a] == vx[c]) {
-                    ylo = fmin(ylo, fmin(vy[a], vy[c]));
-                    yhi = fmax(yhi, fmax(vy[a], vy[c]));
-                } else {
-                    const double y = vy[a] + (vy[c] - vy[a]) * (da / (vx[a] - vx[c]));
-                    ylo = fmin(ylo, y);
-                    yhi = fmax(yhi, y);
-                }
-            }
+        for (int c = a + 1; c < 4; ++c, ++k) {
+            const double da = sh.vx[a] - cx, dc = sh.vx[c] - cx;
+            const bool meets = da * dc <= 0.0;
+            const bool flat = sh.vx[a] == sh.vx[c];
+            const double y = fma(sh.vy[c] - sh.vy[a], da * sh.inv[k], sh.vy[a]);
+            const double lo = flat ? fmin(sh.vy[a], sh.vy[c]) : y;
+            const double hi = flat ? fmax(sh.vy[a], sh.vy[c]) : y;
+            ylo = meets ? fmin(ylo, lo) : ylo;
+            yhi = meets ? fmax(yhi, hi) : yhi;
         }
     }
     // centers (2j+1)S with ylo - 1 <= (2j+1)S <= yhi + 1
@@ -478,13 +523,15 @@ __global__ void __launch_bounds__(kTileThreads)
             // phase 1a: one lane per piece: clipped box, faces -> record
             const uint32_t pi = pb + tid;
             int32_t lo[3] = {0, 0, 0}, hi[3] = {-1, -1, -1};
-            double vx[4], vy[4];
+            int4 Vt[4];
             uint32_t nrows = 0;
             if (pi < p1) {
                 const int4 Tt = tets[b.pieces[pi] - tbase];
                 const int4 A = q4[Tt.x], B = q4[Tt.y], C = q4[Tt.z], D = q4[Tt.w];
-                vx[0] = A.x; vx[1] = B.x; vx[2] = C.x; vx[3] = D.x;
-                vy[0] = A.y; vy[1] = B.y; vy[2] = C.y; vy[3] = D.y;
+                Vt[0] = A;
+                Vt[1] = B;
+                Vt[2] = C;
+                Vt[3] = D;
                 candidate_box(A, B, C, D, g, lo, hi);
                 lo[0] = max(lo[0], ti0);
                 hi[0] = min(hi[0], ti1);
@@ -525,11 +572,13 @@ __global__ void __launch_bounds__(kTileThreads)
             if ((uint32_t)tid < nb && nrows) {
                 PieceRec &R = s_rec[tid];
                 const uint32_t base = s_roff[tid];
+                Silhouette sh;
+                make_silhouette(Vt, sh);
                 uint32_t prefix = 0;
                 for (uint32_t rr = 0; rr < nrows; ++rr) {
                     const double cx = (double)((2 * (lo[0] + (int32_t)rr) + 1) * g.half[0]);
                     int32_t j0, j1;
-                    row_columns(vx, vy, cx, g, j0, j1);
+                    row_columns(sh, cx, g, j0, j1);
                     j0 = max(j0, lo[1]);
                     j1 = min(j1, hi[1]);
                     const uint32_t cnt = j1 >= j0 ? (uint32_t)(j1 - j0 + 1) : 0u;
@@ -576,9 +625,21 @@ __global__ void __launch_bounds__(kTileThreads)
                 int32_t di = (int32_t)ra;
                 int32_t dj = (int32_t)(rw & 0xffu) + (int32_t)(c0 - (rw >> 16));
                 int32_t jend = (int32_t)(rw & 0xffu) + (int32_t)((rw >> 8) & 0xffu);
+                // face values at the current column; exact integers, advanced
+                // by SY per column along a row and recomputed on a row change
+                double a[4];
+#pragma unroll
+                for (int fi = 0; fi < 4; ++fi)
+                    a[fi] = fma(f[fi].SY, (double)dj, fma(f[fi].SX, (double)di, f[fi].A));
                 for (uint32_t c = c0; c < c1; ++c) {
-                    int32_t zlo, zhi;
-                    column_span(f, lower, (double)di, (double)dj, nk, nkd, zlo, zhi);
+                    int32_t zlo = 0, zhi = nk;
+#pragma unroll
+                    for (int fi = 0; fi < 4; ++fi) {
+                        const int32_t t = face_threshold(f[fi], a[fi], nkd);
+                        const bool isl = (lower >> fi) & 1u;
+                        zlo = isl ? max(zlo, t) : zlo;
+                        zhi = isl ? zhi : min(zhi, t);
+                    }
                     if (zlo < zhi)
                         or_run_lds(s_bits + (((ci0 + di) << p.ly) + cj0 + dj) * tw, k0 + zlo,
                                    k0 + zhi);
@@ -590,6 +651,12 @@ __global__ void __launch_bounds__(kTileThreads)
                         } while (((rw >> 8) & 0xffu) == 0u);
                         dj = (int32_t)(rw & 0xffu);
                         jend = dj + (int32_t)((rw >> 8) & 0xffu);
+#pragma unroll
+                        for (int fi = 0; fi < 4; ++fi)
+                            a[fi] = fma(f[fi].SY, (double)dj, fma(f[fi].SX, (double)di, f[fi].A));
+                    } else {
+#pragma unroll
+                        for (int fi = 0; fi < 4; ++fi) a[fi] += f[fi].SY;
                     }
                 }
             }
