@@ -359,7 +359,7 @@ constexpr int kRowPool = 4096;       // per-batch row entries (16 KiB)
 struct PieceRec {
     Face f[4];
     int16_t ci0, cj0;   // tile-local column origin of the clipped box
-    int16_t ni, k0;     // rows (x extent) of the clipped box; tile-local first z index
+    int16_t ni, k0;     // row-pool entries (non-empty rows); tile-local first z index
     int16_t nk;         // z extent
     uint16_t lower;     // faces that start the span
     uint16_t row0;      // first entry of this piece's rows in the row pool
@@ -381,50 +381,53 @@ __device__ __forceinline__ void column_span(const Face f[4], uint32_t lower, dou
     }
 }
 
-// Vertex projections of a tet for the per-row culling below: x and y of the
-// 4 vertices and, per vertex pair, 1/(x_a - x_c) (0 for a pair at equal x).
-struct Silhouette {
-    double vx[4], vy[4], inv[6];
+// The tet's projection onto the xy plane is a convex polygon: the hull of
+// the 4 projected vertices.  Each vertex pair (a, c) with x_a != x_c spans a
+// line y = m x + b; it is a lower hull edge when the other two vertices lie
+// on or above it, an upper one when they lie on or below it.  For x inside
+// the polygon's x range, the polygon's cross-section is then
+// [max over lower lines, min over upper lines].  A line that bounds no side
+// carries -inf / +inf as its intercept so that max / min ignore it.  The
+// side tests are exact (products of lattice differences stay below 2^37).
+struct RowHull {
+    double m[6], bl[6], bu[6];
 };
 
-__device__ __forceinline__ void make_silhouette(const int4 V[4], Silhouette &s) {
+__device__ __forceinline__ void make_row_hull(const int4 V[4], RowHull &h) {
+    constexpr int pa[6] = {0, 0, 0, 1, 1, 2}, pc[6] = {1, 2, 3, 2, 3, 3};
+    constexpr int po[6] = {2, 1, 1, 0, 0, 0}, pq[6] = {3, 3, 2, 3, 2, 1};
+    const double inf = __builtin_huge_val();
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        s.vx[a] = (double)V[a].x;
-        s.vy[a] = (double)V[a].y;
+    for (int k = 0; k < 6; ++k) {
+        const int4 A = V[pa[k]], C = V[pc[k]], P = V[po[k]], Q = V[pq[k]];
+        const double dx = (double)(C.x - A.x), dy = (double)(C.y - A.y);
+        // sign-normalised so that a positive side means "above the line"
+        const double sp = dx * (double)(P.y - A.y) - dy * (double)(P.x - A.x);
+        const double sq = dx * (double)(Q.y - A.y) - dy * (double)(Q.x - A.x);
+        const double up = dx > 0.0 ? 1.0 : -1.0;
+        const double ap = sp * up, aq = sq * up;
+        const bool line = dx != 0.0;
+        const double m = line ? dy / dx : 0.0;
+        const double b = fma(-m, (double)A.x, (double)A.y);
+        h.m[k] = m;
+        h.bl[k] = (line && ap >= 0.0 && aq >= 0.0) ? b : -inf;
+        h.bu[k] = (line && ap <= 0.0 && aq <= 0.0) ? b : inf;
     }
-    int k = 0;
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int c = a + 1; c < 4; ++c, ++k)
-            s.inv[k] = s.vx[a] != s.vx[c] ? 1.0 / (s.vx[a] - s.vx[c]) : 0.0;
 }
 
-// Columns of row x = cx (lattice) that the tet's projection onto the xy
-// plane can reach: the cross-section of the tet's vertex hull with the plane
-// x = cx spans y in [ylo, yhi], the extremes over the 6 vertex pairs whose
-// segment meets the plane (both ends for a pair lying in the plane).
-// Evaluated in double with a one-unit margin on each side (conservative);
-// the exact span test decides every column kept.  Returns the inclusive
-// index range [j0, j1] (empty when j0 > j1).
-__device__ __forceinline__ void row_columns(const Silhouette &sh, double cx, const GridGeom &g,
+// Columns of row x = cx (lattice, inside the tet's x range) that the tet's
+// xy projection can reach, with a one-unit margin on each side (the line
+// evaluation is accurate to far better than that, so the range is
+// conservative); the exact span test decides every column kept.  Returns
+// the inclusive index range [j0, j1] (empty when j0 > j1).
+__device__ __forceinline__ void row_columns(const RowHull &h, double cx, const GridGeom &g,
                                             int32_t &j0, int32_t &j1) {
-    double ylo = 1e300, yhi = -1e300;
-    int k = 0;
+    // finite start values keep the conversions below in range
+    double ylo = -1048576.0, yhi = 1048576.0;
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-#pragma unroll
-        for (int c = a + 1; c < 4; ++c, ++k) {
-            const double da = sh.vx[a] - cx, dc = sh.vx[c] - cx;
-            const bool meets = da * dc <= 0.0;
-            const bool flat = sh.vx[a] == sh.vx[c];
-            const double y = fma(sh.vy[c] - sh.vy[a], da * sh.inv[k], sh.vy[a]);
-            const double lo = flat ? fmin(sh.vy[a], sh.vy[c]) : y;
-            const double hi = flat ? fmax(sh.vy[a], sh.vy[c]) : y;
-            ylo = meets ? fmin(ylo, lo) : ylo;
-            yhi = meets ? fmax(yhi, hi) : yhi;
-        }
+    for (int k = 0; k < 6; ++k) {
+        ylo = fmax(ylo, fma(h.m[k], cx, h.bl[k]));
+        yhi = fmin(yhi, fma(h.m[k], cx, h.bu[k]));
     }
     // centers (2j+1)S with ylo - 1 <= (2j+1)S <= yhi + 1
     const double S = (double)g.half[1], inv = 1.0 / (2.0 * S);
@@ -468,7 +471,8 @@ __global__ void __launch_bounds__(kTileThreads)
     k_tile_voxelize(MeshTable T, BinBuffers b, int strict) {
     __shared__ uint32_t s_bits[kMaxTileWords];
     __shared__ PieceRec s_rec[kTileThreads];
-    __shared__ uint32_t s_row[kRowPool];  // j0 (8 bits) | count (8 bits) | prefix (16 bits)
+    // non-empty rows: j0 (8 bits) | count (8 bits) | di (6 bits) | prefix (10 bits)
+    __shared__ uint32_t s_row[kRowPool];
     __shared__ uint32_t s_soff[kTileThreads + 1];
     __shared__ uint32_t s_roff[kTileThreads + 1];
     __shared__ uint32_t s_chunk, s_tile, s_p0, s_p1, s_shared, s_nb;
@@ -572,20 +576,23 @@ __global__ void __launch_bounds__(kTileThreads)
             if ((uint32_t)tid < nb && nrows) {
                 PieceRec &R = s_rec[tid];
                 const uint32_t base = s_roff[tid];
-                Silhouette sh;
-                make_silhouette(Vt, sh);
-                uint32_t prefix = 0;
+                RowHull hull;
+                make_row_hull(Vt, hull);
+                uint32_t prefix = 0, kept = 0;
                 for (uint32_t rr = 0; rr < nrows; ++rr) {
                     const double cx = (double)((2 * (lo[0] + (int32_t)rr) + 1) * g.half[0]);
                     int32_t j0, j1;
-                    row_columns(sh, cx, g, j0, j1);
+                    row_columns(hull, cx, g, j0, j1);
                     j0 = max(j0, lo[1]);
                     j1 = min(j1, hi[1]);
-                    const uint32_t cnt = j1 >= j0 ? (uint32_t)(j1 - j0 + 1) : 0u;
-                    const uint32_t jrel = j1 >= j0 ? (uint32_t)(j0 - lo[1]) : 0u;
-                    s_row[base + rr] = jrel | (cnt << 8) | (prefix << 16);
-                    prefix += cnt;
+                    if (j1 >= j0) {
+                        const uint32_t cnt = (uint32_t)(j1 - j0 + 1);
+                        s_row[base + kept] = (uint32_t)(j0 - lo[1]) | (cnt << 8) | (rr << 16) | (prefix << 22);
+                        ++kept;
+                        prefix += cnt;
+                    }
                 }
+                R.ni = (int16_t)kept;
                 R.row0 = (uint16_t)base;
                 R.ncols = (uint16_t)prefix;
                 nstrips = (prefix + strip - 1) / strip;
@@ -610,32 +617,32 @@ __global__ void __launch_bounds__(kTileThreads)
                 for (int fi = 0; fi < 4; ++fi) f[fi] = R.f[fi];
                 const uint32_t lower = R.lower;
                 const int32_t nk = R.nk, k0 = R.k0, ci0 = R.ci0, cj0 = R.cj0;
-                const uint32_t row0 = R.row0, ni = (uint32_t)R.ni;
+                const uint32_t row0 = R.row0, nr = (uint32_t)R.ni;
                 const double nkd = (double)nk;
                 const uint32_t c0 = (s - s_soff[lo_r]) * strip;
                 const uint32_t c1 = min(c0 + strip, (uint32_t)R.ncols);
-                // row holding kept column c0: last row with prefix <= c0
-                uint32_t ra = 0, rb = ni;
+                // row entry holding kept column c0: last entry with prefix <= c0
+                uint32_t ra = 0, rb = nr;
                 while (rb - ra > 1) {
                     const uint32_t mid = (ra + rb) >> 1;
-                    if ((s_row[row0 + mid] >> 16) <= c0) ra = mid;
+                    if ((s_row[row0 + mid] >> 22) <= c0) ra = mid;
                     else rb = mid;
                 }
-                uint32_t rw = s_row[row0 + ra];
-                int32_t di = (int32_t)ra;
-                int32_t dj = (int32_t)(rw & 0xffu) + (int32_t)(c0 - (rw >> 16));
+                uint32_t r = row0 + ra;
+                const uint32_t rw = s_row[r];
+                int32_t di = (int32_t)((rw >> 16) & 63u);
+                int32_t dj = (int32_t)(rw & 0xffu) + (int32_t)(c0 - (rw >> 22));
                 int32_t jend = (int32_t)(rw & 0xffu) + (int32_t)((rw >> 8) & 0xffu);
-                // face values at the current column; exact integers, advanced
-                // by SY per column along a row and recomputed on a row change
-                double a[4];
-#pragma unroll
-                for (int fi = 0; fi < 4; ++fi)
-                    a[fi] = fma(f[fi].SY, (double)dj, fma(f[fi].SX, (double)di, f[fi].A));
                 for (uint32_t c = c0; c < c1; ++c) {
+                    // the next row entry, read one column ahead (used only on a
+                    // row change, which happens only while columns remain)
+                    const uint32_t nx = s_row[min(r + 1, (uint32_t)kRowPool - 1)];
+                    const double ddi = (double)di, ddj = (double)dj;
                     int32_t zlo = 0, zhi = nk;
 #pragma unroll
                     for (int fi = 0; fi < 4; ++fi) {
-                        const int32_t t = face_threshold(f[fi], a[fi], nkd);
+                        const double a = fma(f[fi].SY, ddj, fma(f[fi].SX, ddi, f[fi].A));
+                        const int32_t t = face_threshold(f[fi], a, nkd);
                         const bool isl = (lower >> fi) & 1u;
                         zlo = isl ? max(zlo, t) : zlo;
                         zhi = isl ? zhi : min(zhi, t);
@@ -643,21 +650,13 @@ __global__ void __launch_bounds__(kTileThreads)
                     if (zlo < zhi)
                         or_run_lds(s_bits + (((ci0 + di) << p.ly) + cj0 + dj) * tw, k0 + zlo,
                                    k0 + zhi);
-                    if (++dj == jend && c + 1 < c1) {
-                        // next row with kept columns
-                        do {
-                            ++di;
-                            rw = s_row[row0 + di];
-                        } while (((rw >> 8) & 0xffu) == 0u);
-                        dj = (int32_t)(rw & 0xffu);
-                        jend = dj + (int32_t)((rw >> 8) & 0xffu);
-#pragma unroll
-                        for (int fi = 0; fi < 4; ++fi)
-                            a[fi] = fma(f[fi].SY, (double)dj, fma(f[fi].SX, (double)di, f[fi].A));
-                    } else {
-#pragma unroll
-                        for (int fi = 0; fi < 4; ++fi) a[fi] += f[fi].SY;
-                    }
+                    // advance along the row, or to the next non-empty row
+                    const bool wrap = ++dj == jend;
+                    r += wrap ? 1u : 0u;
+                    const int32_t nj0 = (int32_t)(nx & 0xffu);
+                    di = wrap ? (int32_t)((nx >> 16) & 63u) : di;
+                    dj = wrap ? nj0 : dj;
+                    jend = wrap ? nj0 + (int32_t)((nx >> 8) & 0xffu) : jend;
                 }
             }
             __syncthreads();
