@@ -602,61 +602,90 @@ __global__ void __launch_bounds__(kTileThreads)
             __syncthreads();
             scan256_wave0(s_soff, tid, nullptr, 0xffffffffu);
             __syncthreads();
-            // phase 3: strips of `strip` kept columns, one per lane
+            // phase 3: the batch's kept columns in strips of `strip`; each lane
+            // takes a contiguous block of strips, so its faces and its row
+            // position carry over from one strip to the next of the same piece
             const uint32_t nst = s_soff[kTileThreads];
-            for (uint32_t s = tid; s < nst; s += kTileThreads) {
-                int32_t lo_r = 0, hi_r = kTileThreads;  // s_soff[lo_r] <= s < s_soff[hi_r]
-                while (hi_r - lo_r > 1) {
-                    const int32_t mid = (lo_r + hi_r) >> 1;
-                    if (s_soff[mid] <= s) lo_r = mid;
+            const uint32_t sb = (uint32_t)(((uint64_t)nst * (uint32_t)tid) / kTileThreads);
+            const uint32_t se = (uint32_t)(((uint64_t)nst * (uint32_t)(tid + 1)) / kTileThreads);
+            if (sb < se) {
+                int32_t pc = 0, hi_r = kTileThreads;  // s_soff[pc] <= sb < s_soff[hi_r]
+                while (hi_r - pc > 1) {
+                    const int32_t mid = (pc + hi_r) >> 1;
+                    if (s_soff[mid] <= sb) pc = mid;
                     else hi_r = mid;
                 }
-                const PieceRec &R = s_rec[lo_r];
                 Face f[4];
+                int32_t mlo[4];  // -1 for a face that starts the span, 0 for one that ends it
+                int32_t nk = 0, k0 = 0, ci0 = 0, cj0 = 0, di = 0, dj = 0, jend = 0;
+                uint32_t ncols = 0, pfirst = 0, pend = 0, r = 0;
+                double nkd = 0.0;
+                bool first = true;
+                for (uint32_t s = sb; s < se; ++s) {
+                    if (first || s == pend) {
+                        // (next) piece with strips, positioned at its first
+                        // column in this lane's block
+                        if (!first)
+                            do ++pc;
+                            while (s_soff[pc + 1] <= s);
+                        first = false;
+                        const PieceRec &R = s_rec[pc];
 #pragma unroll
-                for (int fi = 0; fi < 4; ++fi) f[fi] = R.f[fi];
-                const uint32_t lower = R.lower;
-                const int32_t nk = R.nk, k0 = R.k0, ci0 = R.ci0, cj0 = R.cj0;
-                const uint32_t row0 = R.row0, nr = (uint32_t)R.ni;
-                const double nkd = (double)nk;
-                const uint32_t c0 = (s - s_soff[lo_r]) * strip;
-                const uint32_t c1 = min(c0 + strip, (uint32_t)R.ncols);
-                // row entry holding kept column c0: last entry with prefix <= c0
-                uint32_t ra = 0, rb = nr;
-                while (rb - ra > 1) {
-                    const uint32_t mid = (ra + rb) >> 1;
-                    if ((s_row[row0 + mid] >> 22) <= c0) ra = mid;
-                    else rb = mid;
-                }
-                uint32_t r = row0 + ra;
-                const uint32_t rw = s_row[r];
-                int32_t di = (int32_t)((rw >> 16) & 63u);
-                int32_t dj = (int32_t)(rw & 0xffu) + (int32_t)(c0 - (rw >> 22));
-                int32_t jend = (int32_t)(rw & 0xffu) + (int32_t)((rw >> 8) & 0xffu);
-                for (uint32_t c = c0; c < c1; ++c) {
-                    // the next row entry, read one column ahead (used only on a
-                    // row change, which happens only while columns remain)
-                    const uint32_t nx = s_row[min(r + 1, (uint32_t)kRowPool - 1)];
-                    const double ddi = (double)di, ddj = (double)dj;
-                    int32_t zlo = 0, zhi = nk;
-#pragma unroll
-                    for (int fi = 0; fi < 4; ++fi) {
-                        const double a = fma(f[fi].SY, ddj, fma(f[fi].SX, ddi, f[fi].A));
-                        const int32_t t = face_threshold(f[fi], a, nkd);
-                        const bool isl = (lower >> fi) & 1u;
-                        zlo = isl ? max(zlo, t) : zlo;
-                        zhi = isl ? zhi : min(zhi, t);
+                        for (int fi = 0; fi < 4; ++fi) {
+                            f[fi] = R.f[fi];
+                            mlo[fi] = ((R.lower >> fi) & 1u) ? -1 : 0;
+                        }
+                        nk = R.nk;
+                        k0 = R.k0;
+                        ci0 = R.ci0;
+                        cj0 = R.cj0;
+                        ncols = R.ncols;
+                        nkd = (double)nk;
+                        pfirst = s_soff[pc];
+                        pend = s_soff[pc + 1];
+                        const uint32_t row0 = R.row0;
+                        const uint32_t cs = (s - pfirst) * strip;
+                        // row entry holding kept column cs: last entry with prefix <= cs
+                        uint32_t ra = 0, rb = cs ? (uint32_t)R.ni : 1u;
+                        while (rb - ra > 1) {
+                            const uint32_t mid = (ra + rb) >> 1;
+                            if ((s_row[row0 + mid] >> 22) <= cs) ra = mid;
+                            else rb = mid;
+                        }
+                        r = row0 + ra;
+                        const uint32_t rw = s_row[r];
+                        di = (int32_t)((rw >> 16) & 63u);
+                        dj = (int32_t)(rw & 0xffu) + (int32_t)(cs - (rw >> 22));
+                        jend = (int32_t)(rw & 0xffu) + (int32_t)((rw >> 8) & 0xffu);
                     }
-                    if (zlo < zhi)
-                        or_run_lds(s_bits + (((ci0 + di) << p.ly) + cj0 + dj) * tw, k0 + zlo,
-                                   k0 + zhi);
-                    // advance along the row, or to the next non-empty row
-                    const bool wrap = ++dj == jend;
-                    r += wrap ? 1u : 0u;
-                    const int32_t nj0 = (int32_t)(nx & 0xffu);
-                    di = wrap ? (int32_t)((nx >> 16) & 63u) : di;
-                    dj = wrap ? nj0 : dj;
-                    jend = wrap ? nj0 + (int32_t)((nx >> 8) & 0xffu) : jend;
+                    const uint32_t c0 = (s - pfirst) * strip;
+                    const uint32_t c1 = min(c0 + strip, ncols);
+                    for (uint32_t c = c0; c < c1; ++c) {
+                        // the next row entry, read one column ahead (used only on a
+                        // row change, which happens only while columns remain)
+                        const uint32_t nx = s_row[min(r + 1, (uint32_t)kRowPool - 1)];
+                        const double ddi = (double)di, ddj = (double)dj;
+                        int32_t tl[4], tu[4];
+#pragma unroll
+                        for (int fi = 0; fi < 4; ++fi) {
+                            const double a = fma(f[fi].SY, ddj, fma(f[fi].SX, ddi, f[fi].A));
+                            const int32_t t = face_threshold(f[fi], a, nkd);  // in [0, nk + 1]
+                            tl[fi] = t & mlo[fi];                              // 0: no lower bound
+                            tu[fi] = (t & ~mlo[fi]) | (nk & mlo[fi]);          // nk: no upper bound
+                        }
+                        const int32_t zlo = max(max(tl[0], tl[1]), max(tl[2], tl[3]));
+                        const int32_t zhi = min(min(tu[0], tu[1]), min(min(tu[2], tu[3]), nk));
+                        if (zlo < zhi)
+                            or_run_lds(s_bits + (((ci0 + di) << p.ly) + cj0 + dj) * tw, k0 + zlo,
+                                       k0 + zhi);
+                        // advance along the row, or to the next non-empty row
+                        const bool wrap = ++dj == jend;
+                        r += wrap ? 1u : 0u;
+                        const int32_t nj0 = (int32_t)(nx & 0xffu);
+                        di = wrap ? (int32_t)((nx >> 16) & 63u) : di;
+                        dj = wrap ? nj0 : dj;
+                        jend = wrap ? nj0 + (int32_t)((nx >> 8) & 0xffu) : jend;
+                    }
                 }
             }
             __syncthreads();
