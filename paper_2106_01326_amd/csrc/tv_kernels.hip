@@ -350,6 +350,27 @@ __global__ void k_zero_shared_tiles(MeshTable T, BinBuffers b) {
     }
 }
 
+// Global-address-space views of device arrays: loads through them are
+// global (not flat) loads, which do not count against the LDS wait counter.
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename T>
+using gptr = const __attribute__((address_space(1))) T *;
+#else
+template <typename T>
+using gptr = const T *;  // host pass: kernels are only parsed there
+#endif
+template <typename T>
+__device__ __forceinline__ gptr<T> as_global(const T *p) {
+    return (gptr<T>)p;
+}
+struct alignas(16) Int4Rec {
+    int32_t x, y, z, w;
+};
+__device__ __forceinline__ int4 load_int4(gptr<int4> base, int64_t i) {
+    const Int4Rec r = ((gptr<Int4Rec>)base)[i];
+    return make_int4(r.x, r.y, r.z, r.w);
+}
+
 // ------------------------------------------------------ tile voxelization
 
 constexpr int kTileThreads = 256;
@@ -510,8 +531,9 @@ __global__ void __launch_bounds__(kTileThreads)
         const MeshDesc &d = mesh_desc(T, s_mesh);
         const GridGeom g = d.g;
         const TilePlan p = d.p;
-        const int4 *__restrict__ q4 = b.q4 + d.vert_base;
-        const int4 *__restrict__ tets = d.tets;
+        const gptr<int4> q4 = as_global(b.q4 + d.vert_base);
+        const gptr<int4> tets = as_global(d.tets);
+        const gptr<uint32_t> pieces = as_global(b.pieces);
         const uint32_t tbase = (uint32_t)d.tet_base;
         const int32_t tw = 1 << p.lw;
         const int32_t nwords = (1 << (p.lx + p.ly)) * tw;
@@ -523,6 +545,16 @@ __global__ void __launch_bounds__(kTileThreads)
         const int32_t tk1 = min(tk0 + (tw << 5) - 1, g.n[2] - 1);
 
         uint32_t pb = s_p0;
+        // vertex records of this lane's piece in the next batch; loaded ahead
+        // (the piece id -> tet -> vertex chain is three dependent gathers)
+        int4 Vn[4];
+        if (pb + tid < p1) {
+            const int4 Tt = load_int4(tets, pieces[pb + tid] - tbase);
+            Vn[0] = load_int4(q4, Tt.x);
+            Vn[1] = load_int4(q4, Tt.y);
+            Vn[2] = load_int4(q4, Tt.z);
+            Vn[3] = load_int4(q4, Tt.w);
+        }
         while (pb < p1) {
             // phase 1a: one lane per piece: clipped box, faces -> record
             const uint32_t pi = pb + tid;
@@ -530,8 +562,7 @@ __global__ void __launch_bounds__(kTileThreads)
             int4 Vt[4];
             uint32_t nrows = 0;
             if (pi < p1) {
-                const int4 Tt = tets[b.pieces[pi] - tbase];
-                const int4 A = q4[Tt.x], B = q4[Tt.y], C = q4[Tt.z], D = q4[Tt.w];
+                const int4 A = Vn[0], B = Vn[1], C = Vn[2], D = Vn[3];
                 Vt[0] = A;
                 Vt[1] = B;
                 Vt[2] = C;
@@ -571,6 +602,11 @@ __global__ void __launch_bounds__(kTileThreads)
             scan256_wave0(s_roff, tid, &s_nb, (uint32_t)kRowPool);
             __syncthreads();
             const uint32_t nb = min(s_nb, p1 - pb);
+            // the next batch's tet record, then (after phase 1c) its vertices
+            // (unconditional, with the index clamped to this chunk's last piece,
+            // so that nothing waits for it before its use)
+            const uint32_t pn = pb + nb + tid;
+            int4 Tn = load_int4(tets, pieces[min(pn, p1 - 1)] - tbase);
             // phase 1c: per-row column ranges of the pieces in this batch
             uint32_t nstrips = 0;
             if ((uint32_t)tid < nb && nrows) {
@@ -596,6 +632,14 @@ __global__ void __launch_bounds__(kTileThreads)
                 R.row0 = (uint16_t)base;
                 R.ncols = (uint16_t)prefix;
                 nstrips = (prefix + strip - 1) / strip;
+            }
+            // keeps the use of the tet record (and so its wait) after phase 1c
+            asm volatile("" : "+v"(Tn.x), "+v"(Tn.y), "+v"(Tn.z), "+v"(Tn.w));
+            if (pn < p1) {
+                Vn[0] = load_int4(q4, Tn.x);
+                Vn[1] = load_int4(q4, Tn.y);
+                Vn[2] = load_int4(q4, Tn.z);
+                Vn[3] = load_int4(q4, Tn.w);
             }
             // phase 2: exclusive scan of strip counts
             s_soff[tid] = nstrips;
