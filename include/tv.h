@@ -90,7 +90,7 @@ typedef struct {
 size_t tv_grid_words(tv_dims dims);
 
 /* Workspace bytes needed by tv_voxelize / tv_voxelize_q for these sizes
- * (about 16 bytes per vertex plus 36 bytes per tet plus a few bytes per
+ * (about 16 bytes per vertex plus 44 bytes per tet plus a few bytes per
  * grid tile). */
 size_t tv_workspace_bytes(int64_t nv, int64_t nt, tv_dims dims, uint32_t flags);
 

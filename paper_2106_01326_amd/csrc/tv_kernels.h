@@ -73,6 +73,7 @@ struct BinBuffers {
     uint32_t *chunk_off;    // [ntiles + 1] first chunk per tile
     uint32_t *pieces;       // [nt * piece_cap] global tet ids sorted by tile
     uint32_t *big;          // [nt] large tets (global ids)
+    uint2 *trec;            // [nt] tile summary: (first tile key, shape code; 0 = no pieces)
     int4 *q4;               // [nv] lattice vertices (.w = invalid flag)
 };
 

@@ -206,26 +206,45 @@ __device__ __forceinline__ int32_t tet_pieces(const MeshDesc &d, const int4 *__r
 // tile), then one global atomic per distinct key adds the workgroup's
 // count (pass 1) or reserves its slot range (pass 2).  Neighbouring tets,
 // which mostly share tiles, thus cost one global atomic per workgroup and
-// tile instead of one per piece.
+// tile instead of one per piece.  A key that finds no free slot within
+// kHashProbes probes (a workgroup meeting very many tiles, e.g. shuffled
+// tets) takes its own global atomic instead, so the table never has to
+// hold every key.  The counting pass leaves a per-tet summary (first tile
+// key and the tile range's shape), so the scatter pass reads 8 bytes per tet
+// instead of gathering and boxing the tet again.
 constexpr int kBinThreads = 256;
-constexpr int kHashSlots = 2048;  // >= kBinThreads * kPieceCapMax: every probe ends
+constexpr int kHashSlots = 512;
+constexpr int kHashProbes = 32;
 constexpr int kPieceCapMax = 8;
 constexpr uint32_t kEmptyKey = 0xffffffffu;
+constexpr uint32_t kNoSlot = 0xffffffffu;
 
+// Slot of `key` in the table, inserting it if needed; kNoSlot when the
+// probe sequence is exhausted.
 __device__ __forceinline__ uint32_t hash_insert(uint32_t *keys, uint32_t key) {
-    uint32_t h = (key * 2654435761u) >> (32 - 11);
-    for (;;) {
+    uint32_t h = (key * 2654435761u) >> (32 - 9);
+    for (int i = 0; i < kHashProbes; ++i) {
         const uint32_t prev = atomicCAS(keys + h, kEmptyKey, key);
         if (prev == kEmptyKey || prev == key) return h;
         h = (h + 1) & (kHashSlots - 1);
     }
+    return kNoSlot;
+}
+
+// Tile summary of a tet: x (the first tile's global key) and y = 0 when the
+// tet has no pieces, else 1 | (nx-1) << 1 | (ny-1) << 4 | (nz-1) << 7 for a
+// tile range of nx * ny * nz <= kPieceCapMax tiles.
+__device__ __forceinline__ uint2 encode_trec(uint32_t key0, const TileRange &r, int32_t np) {
+    if (np == 0) return make_uint2(0u, 0u);
+    return make_uint2(key0, 1u | (uint32_t)(r.x1 - r.x0) << 1 | (uint32_t)(r.y1 - r.y0) << 4 |
+                                (uint32_t)(r.z1 - r.z0) << 7);
 }
 
 template <bool kScatter>
 __global__ void __launch_bounds__(kBinThreads) k_bin(MeshTable T, BinBuffers b) {
     __shared__ uint32_t s_key[kHashSlots];
     __shared__ uint32_t s_cnt[kHashSlots];  // count, then (pass 2) global slot base
-    __shared__ uint32_t s_ref[kBinThreads * kPieceCapMax];  // slot << 16 | rank
+    __shared__ uint32_t s_ref[kBinThreads * kPieceCapMax];  // slot << 16 | rank, or kNoSlot
     __shared__ int32_t s_bracket[2];
     const int tid = threadIdx.x;
     for (int i = tid; i < kHashSlots; i += kBinThreads) {
@@ -240,22 +259,44 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(MeshTable T, BinBuffers b) 
     int32_t np = 0;
     if (t < T.nt_total) {
         const MeshDesc &d = mesh_desc(T, m);
-        TileRange r = {0, -1, 0, -1, 0, -1};
-        // status flags are raised by the counting pass only
-        np = tet_pieces(d, b.q4, t - d.tet_base, kScatter ? nullptr : b.status, r);
-        if (np > T.piece_cap) {
-            if (!kScatter) b.big[atomicAdd(&b.meta[kMetaBig], 1u)] = (uint32_t)t;
-            np = 0;
+        uint32_t key0 = 0;
+        int32_t nx = 1, ny = 1, nz = 1;
+        if (!kScatter) {
+            TileRange r = {0, -1, 0, -1, 0, -1};
+            np = tet_pieces(d, b.q4, t - d.tet_base, b.status, r);
+            if (np > T.piece_cap) {
+                b.big[atomicAdd(&b.meta[kMetaBig], 1u)] = (uint32_t)t;
+                np = 0;
+            }
+            key0 = (uint32_t)d.tile_base + tile_id(r.x0, r.y0, r.z0, d.p);
+            b.trec[t] = encode_trec(key0, r, np);
+            ny = r.y1 - r.y0 + 1;
+            nz = r.z1 - r.z0 + 1;
+        } else {
+            const uint2 rec = b.trec[t];
+            if (rec.y) {
+                key0 = rec.x;
+                nx = (int32_t)((rec.y >> 1) & 7u) + 1;
+                ny = (int32_t)((rec.y >> 4) & 7u) + 1;
+                nz = (int32_t)((rec.y >> 7) & 7u) + 1;
+                np = nx * ny * nz;
+            }
         }
-        const uint32_t tbase = (uint32_t)d.tile_base;
-        const int32_t ny_ = r.y1 - r.y0 + 1, nz_ = r.z1 - r.z0 + 1;
+        const uint32_t sy = (uint32_t)d.p.ntz, sx = (uint32_t)d.p.nty * sy;
         for (int32_t k = 0; k < np; ++k) {
-            const int32_t dz = k % nz_, rest = k / nz_;
-            const int32_t dy = rest % ny_, dx = rest / ny_;
-            const uint32_t key = tbase + tile_id(r.x0 + dx, r.y0 + dy, r.z0 + dz, d.p);
+            const int32_t dz = k % nz, rest = k / nz;
+            const int32_t dy = rest % ny, dx = rest / ny;
+            const uint32_t key = key0 + (uint32_t)dx * sx + (uint32_t)dy * sy + (uint32_t)dz;
             const uint32_t h = hash_insert(s_key, key);
-            const uint32_t rank = atomicAdd(s_cnt + h, 1u);
-            s_ref[tid * kPieceCapMax + k] = (h << 16) | rank;
+            uint32_t ref = kNoSlot;
+            if (h != kNoSlot) {
+                ref = (h << 16) | atomicAdd(s_cnt + h, 1u);
+            } else if (kScatter) {
+                b.pieces[b.tile_off[key] + atomicAdd(b.tile_cursor + key, 1u)] = (uint32_t)t;
+            } else {
+                atomicAdd(b.tile_count + key, 1u);
+            }
+            s_ref[tid * kPieceCapMax + k] = ref;
         }
     }
     __syncthreads();
@@ -269,7 +310,7 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(MeshTable T, BinBuffers b) 
     __syncthreads();
     for (int32_t k = 0; k < np; ++k) {
         const uint32_t ref = s_ref[tid * kPieceCapMax + k];
-        b.pieces[s_cnt[ref >> 16] + (ref & 0xffffu)] = (uint32_t)t;
+        if (ref != kNoSlot) b.pieces[s_cnt[ref >> 16] + (ref & 0xffffu)] = (uint32_t)t;
     }
 }
 

@@ -68,6 +68,7 @@ struct WorkspaceLayout {
     size_t q4;           // nv int4 lattice vertices (.w = invalid flag)
     size_t pieces;       // nt * kPieceCap uint32
     size_t big;          // nt uint32
+    size_t trec;         // nt uint2: per-tet tile summary from the counting pass
     size_t total;
 };
 
@@ -103,6 +104,8 @@ inline WorkspaceLayout layout(const CallSizes &c) {
     off = align256(off + 4 * (size_t)c.nt * (size_t)kPieceCap);
     L.big = off;
     off = align256(off + 4 * (size_t)c.nt);
+    L.trec = off;
+    off = align256(off + 8 * (size_t)c.nt);
     L.total = off;
     return L;
 }
@@ -117,6 +120,7 @@ inline BinBuffers bin_buffers(uint8_t *ws, const WorkspaceLayout &L) {
     b.chunk_off = reinterpret_cast<uint32_t *>(ws + L.chunk_off);
     b.pieces = reinterpret_cast<uint32_t *>(ws + L.pieces);
     b.big = reinterpret_cast<uint32_t *>(ws + L.big);
+    b.trec = reinterpret_cast<uint2 *>(ws + L.trec);
     b.q4 = reinterpret_cast<int4 *>(ws + L.q4);
     return b;
 }

@@ -239,6 +239,27 @@ def test_random_tet_order(oracle_mod):
     assert_same(got, oracle_words(oracle_mod, m), "shuffled")
 
 
+def test_tets_straddling_tile_corners(oracle_mod):
+    """Small tets placed at random tile corners, in random order: every tet
+    meets up to 8 tiles and a workgroup of the binning passes meets far more
+    distinct tiles than its aggregation table holds, so many pieces take the
+    direct global-atomic path of both passes."""
+    rng = np.random.default_rng(1005)
+    dims = (256, 256, 256)
+    pitch = LAT // 256  # lattice units per voxel
+    n = 2048
+    corner = np.stack([rng.integers(1, 16, n) * 16, rng.integers(1, 16, n) * 16,
+                       np.full(n, 128)], axis=1) * pitch
+    q = (corner[:, None, :] + rng.integers(-6 * pitch, 6 * pitch + 1, size=(n, 4, 3))).reshape(-1, 3)
+    tets = np.arange(4 * n, dtype=np.int32).reshape(n, 4)
+    banner(f"{n} tets at tile corners, {dims}")
+    got, st = gpu_voxelize_q(q, tets, dims)
+    assert st == 0
+    want = oracle_mod.voxelize_q(q.astype(np.int32), tets, dims)
+    assert int(np.unpackbits(want.view(np.uint8)).sum()) > 0
+    assert_same(got, want, "tile-corner tets")
+
+
 def test_repeatable_bit_identical():
     m = synth.make_mesh(16, 0.4, 64, "ellipsoids", 4, 707)
     ref, _ = gpu_voxelize_mesh(m)
