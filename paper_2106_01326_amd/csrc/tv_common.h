@@ -81,7 +81,7 @@ __device__ __forceinline__ bool lex_positive(double gx, double gy, double gz) {
 // for a < 0.  All values are exact integers held in doubles, except R.
 struct Face {
     double A, SX, SY, S;
-    float R;  // estimate of 1/S (relative error <= 2^-24), or 2^60 when S = 0
+    float R;  // estimate of 1/S (relative error < 2^-22), or 2^60 when S = 0
 };
 
 // Builds the four faces of tet (A,B,C,D) (lattice coordinates) relative to
@@ -132,34 +132,34 @@ __device__ __forceinline__ bool build_faces(const int4 &A, const int4 &B, const 
         const double sx = n[0] * (double)(2 * g.half[0]);
         const double sy = n[1] * (double)(2 * g.half[1]);
         const double sz = n[2] * (double)(2 * g.half[2]);
-        if (sz >= 0.0) {
-            // lower (or vertical): span starts at the first dk with L0 + sz dk >= 0
-            f[fi].A = L0;
-            f[fi].SX = sx;
-            f[fi].SY = sy;
-            f[fi].S = sz;
-            f[fi].R = sz > 0.0 ? (float)(1.0 / sz) : 1152921504606846976.0f;  // 2^60
-            lower_mask |= 1u << fi;
-        } else {
-            // upper: span ends at the first dk with L0 + sz dk < 0, i.e. with
-            // -(L0 + sz dk) - 1 >= 0
-            f[fi].A = -L0 - 1.0;
-            f[fi].SX = -sx;
-            f[fi].SY = -sy;
-            f[fi].S = -sz;
-            f[fi].R = (float)(1.0 / (-sz));
-        }
+        // lower (or vertical, sz >= 0): span starts at the first dk with
+        // L0 + sz dk >= 0.  Upper (sz < 0): span ends at the first dk with
+        // L0 + sz dk < 0, i.e. with -(L0 + sz dk) - 1 >= 0.  Both in the form
+        // A + S dk >= 0 with S >= 0.
+        const bool up = sz < 0.0;
+        const double sg = up ? -1.0 : 1.0;
+        f[fi].A = fma(sg, L0, up ? -1.0 : 0.0);
+        f[fi].SX = sg * sx;
+        f[fi].SY = sg * sy;
+        f[fi].S = sg * sz;
+        f[fi].R = f[fi].S > 0.0 ? __builtin_amdgcn_rcpf((float)f[fi].S)
+                                : 1152921504606846976.0f;  // 2^60
+        lower_mask |= up ? 0u : 1u << fi;
     }
     return true;
 }
 
 // First dk in [0, nk + 1] with a + S*dk >= 0 (at least nk when none in
-// [0, nk-1]).  With x = -a/S the threshold is t = ceil(x).  The estimate
-// y = fma(-a, R, -1/2) has relative error below 2^-23 (R is 1/S rounded to
-// float), so for |x| <= 2^20 it lies in [x - 0.57, x - 0.43] and ceil(y) is
-// t or t - 1; for larger |x| (nk <= 2^15) y and x clamp to the same end of
-// [0, nk].  One exact evaluation of a + S*e at e <= nk (a center at most one
-// voxel past the box, still inside the exactness bound) fixes the estimate.
+// [0, nk-1]).  With x = -a/S the threshold is t = ceil(x).  R is the
+// hardware single-precision reciprocal of S rounded to float (S >= 1, so no
+// denormals): rounding S costs at most 2^-24 and the reciprocal 1 ulp
+// (2^-23), so R is within 2^-22 of 1/S relatively (the argument below holds
+// up to 2^-21).  The estimate y = fma(-a, R, -1/2) then lies, for |x| <= 2^20,
+// in [x - 0.75, x - 0.25], strictly between x - 1 and x, so ceil(y) is t or
+// t - 1; for larger |x| (nk <= 2^15) y and x have the same sign and both
+// exceed nk in magnitude, so they clamp to the same end of [0, nk].  One
+// exact evaluation of a + S*e at e <= nk (a center at most one voxel past
+// the box, still inside the exactness bound) fixes the estimate.
 __device__ __forceinline__ int32_t face_threshold(const Face &f, double a, double nkd) {
     double e = ceil(fma(-a, (double)f.R, -0.5));
     e = fmin(fmax(e, 0.0), nkd);

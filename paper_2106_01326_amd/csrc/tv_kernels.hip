@@ -469,7 +469,11 @@ __device__ __forceinline__ void make_row_hull(const int4 V[4], RowHull &h) {
         const double up = dx > 0.0 ? 1.0 : -1.0;
         const double ap = sp * up, aq = sq * up;
         const bool line = dx != 0.0;
-        const double m = line ? dy / dx : 0.0;
+        // slope from the hardware reciprocal refined by one Newton step
+        // (relative error near 2^-51; the culling margin needs far less)
+        const double r0 = __builtin_amdgcn_rcp(line ? dx : 1.0);
+        const double r1 = fma(r0, fma(-(line ? dx : 1.0), r0, 1.0), r0);
+        const double m = line ? dy * r1 : 0.0;
         const double b = fma(-m, (double)A.x, (double)A.y);
         h.m[k] = m;
         h.bl[k] = (line && ap >= 0.0 && aq >= 0.0) ? b : -inf;
@@ -492,7 +496,7 @@ __device__ __forceinline__ void row_columns(const RowHull &h, double cx, const G
         yhi = fmin(yhi, fma(h.m[k], cx, h.bu[k]));
     }
     // centers (2j+1)S with ylo - 1 <= (2j+1)S <= yhi + 1
-    const double S = (double)g.half[1], inv = 1.0 / (2.0 * S);
+    const double S = (double)g.half[1], inv = ldexp(1.0, -g.shift[1]);  // 1 / 2S
     j0 = (int32_t)ceil((ylo - 1.0 - S) * inv);
     j1 = (int32_t)floor((yhi + 1.0 - S) * inv);
 }
