@@ -295,6 +295,89 @@ def bench_serving(args, torch, tv):
     print(json.dumps(out), flush=True)
 
 
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def bench_grids(args, torch, tv):
+    """Grid consumers on the large mesh's 1024^3 grid: the timed step is one
+    tv_unpack to a dense uint8 tensor (the 3D-CNN input); pooling, float32
+    unpacking and bricks are timed alongside and reported as extras."""
+    log("generating workload large")
+    m = make_workload("large")
+    dev = torch.device("cuda:0")
+    v = torch.from_numpy(m.verts).to(dev)
+    t = torch.from_numpy(m.tets).to(dev)
+    grid, ws = tv.voxelize(v, t, m.dims, m.bbox)
+    torch.cuda.synchronize()
+    del ws
+    nx, ny, nz = m.dims
+    n = nx * ny * nz
+    out = torch.empty((nx, ny, nz), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    ms = timed(lambda: tv.unpack(grid, m.dims, out=out), args.steps, args.warmup)
+    grid_bytes = tv.grid_words(m.dims) * 4
+    alg_bytes = grid_bytes + n  # read the packed grid, write one byte per voxel
+    achieved = alg_bytes / (ms * 1e-3) / 1e9
+    log(f"unpack u8: {ms:.4f} ms, {achieved:.0f} GB/s")
+    extras = {}
+    f32 = torch.empty((nx, ny, nz), dtype=torch.float32, device=dev)
+    ms32 = timed(lambda: tv.unpack(grid, m.dims, dtype=torch.float32, out=f32), 5, 1)
+    extras["unpack_f32"] = {"ms": ms32, "GB_per_s": (grid_bytes + 4 * n) / (ms32 * 1e-3) / 1e9}
+    del f32
+    for f in (2, 4, 8):
+        po = torch.empty((nx // f, ny // f, nz // f), dtype=torch.float32, device=dev)
+        msp = timed(lambda: tv.pool(grid, m.dims, f, tv.POOL_FRACTION, out=po), 5, 1)
+        extras[f"pool_fraction_{f}"] = {"ms": msp, "GB_per_s": (grid_bytes + po.numel() * 4) / (msp * 1e-3) / 1e9}
+    msb = timed(lambda: tv.bricks(grid, m.dims), 5, 1)
+    ids, _, nbr = tv.bricks(grid, m.dims)
+    extras["bricks"] = {"ms_incl_count_readback": msb, "nonempty": nbr,
+                        "of": int(tv.load_library().tv_brick_count_max(tv._dims(m.dims)))}
+    log(f"extras {extras}")
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle.grids as G
+
+        words = grid.cpu().numpy().view(np.uint32)
+        # bounded sample: whole x-slabs of the grid, grown until ~cpu_seconds
+        cores = 1  # numpy unpackbits runs on one thread
+        slabs = 16
+        while True:
+            sl = words[: slabs * ny * (nz // 32)]
+            t0 = time.perf_counter()
+            u = G.unpack(sl, (slabs, ny, nz))
+            dt = time.perf_counter() - t0
+            if dt >= 0.5 * args.cpu_seconds or slabs >= nx:
+                break
+            slabs = min(nx, slabs * 4)
+        gpu_slab = out[:slabs].cpu().numpy()
+        cpu = {"value": slabs * ny * nz / dt, "unit": "voxels/s", "cores": cores, "kind": "oracle",
+               "sample": f"first {slabs} of {nx} x-slabs ({dt:.2f} s wall)",
+               "gpu_bit_exact_on_sample": bool(np.array_equal(u, gpu_slab))}
+    res = {"metric": "voxels unpacked/s (packed grid -> dense uint8)", "value": n / (ms * 1e-3),
+           "unit": "voxels/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
+           "data": "synthetic (grid of the seeded large mesh)",
+           "config": {"workload": "grid consumers on the large mesh's 1024^3 grid", "grid": list(m.dims)},
+           "roofline": {"bound": "hbm", "kernel": "k_unpack16<16>", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                        "algorithmic_bytes_per_launch": alg_bytes},
+           "extras": extras, "cpu_baseline": cpu}
+    print(json.dumps(res), flush=True)
+
+
 def cpu_baseline_batch(meshes, batch, target_s):
     """The oracle on the first meshes of the batch until about target_s of
     wall time; compared bit for bit with the batched GPU grids."""
@@ -323,7 +406,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="large", choices=["large", "medium", "small", "batch", "serving"])
+    ap.add_argument("--workload", default="large",
+                    choices=["large", "medium", "small", "batch", "serving", "grids"])
     ap.add_argument("--requests", type=int, default=10000)
     ap.add_argument("--batch-meshes", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -358,6 +442,8 @@ def main():
         return bench_batch(args, torch, tv)
     if args.workload == "serving":
         return bench_serving(args, torch, tv)
+    if args.workload == "grids":
+        return bench_grids(args, torch, tv)
     log(f"generating workload {args.workload}")
     t0 = time.perf_counter()
     m = make_workload(args.workload)

@@ -251,6 +251,55 @@ tv_status tv_server_get_stats(tv_server *s, tv_server_stats *out);
 /* Waits for in-flight waves, stops the threads and frees everything. */
 tv_status tv_server_destroy(tv_server *s);
 
+/*
+ * Grid consumers (device-side, asynchronous on `stream`, allocate nothing).
+ * The paper motivates solid grids by 3D CNN training data (Section 1; the
+ * 3D CNN connection itself is left to future work in Section 6) and notes
+ * that the sparse nature of voxel data favours sparse storage (Octrees
+ * paragraph, Section 5).  These calls turn a packed grid (layout above)
+ * into what such consumers read.
+ *
+ * tv_unpack: dense tensor out[nx][ny][nz] (z fastest, C order) with 1 for a
+ *   set voxel and 0 otherwise; TV_UNPACK_U8 writes uint8, TV_UNPACK_F32
+ *   float32.  `out` holds nx*ny*nz elements (16-byte alignment selects the
+ *   vectorized path; any alignment of the element type is accepted).
+ *   Errors: TV_ERR_UNSUPPORTED_DIMS, TV_ERR_INVALID_ARG (null, format).
+ */
+#define TV_UNPACK_U8 0u
+#define TV_UNPACK_F32 1u
+tv_status tv_unpack(const uint32_t *grid, tv_dims dims, void *out, uint32_t format, void *stream);
+
+/*
+ * tv_pool: a coarser level by `factor` f (a power of two in [2, 32] that
+ * divides nx, ny and nz); output dims (nx/f, ny/f, nz/f).
+ *   TV_POOL_FRACTION: float32 out[nx/f][ny/f][nz/f] = (set voxels of the
+ *     f^3 block) / f^3, a multiple of 2^-15 computed exactly;
+ *   TV_POOL_ANY: a packed grid of dims / f (same layout, padding bits 0)
+ *     whose voxel is set iff any voxel of its block is.
+ *   Errors: TV_ERR_UNSUPPORTED_DIMS, TV_ERR_INVALID_ARG (factor, mode, null).
+ */
+#define TV_POOL_FRACTION 0u
+#define TV_POOL_ANY 1u
+tv_status tv_pool(const uint32_t *grid, tv_dims dims, int32_t factor, uint32_t mode, void *out,
+                  void *stream);
+
+/*
+ * tv_bricks: the non-empty bricks of a grid, in increasing brick id.  A
+ * brick is 8 x 8 columns by 32 z voxels -- one grid word per column, 256
+ * bytes; brick (bx, by, bz) has id (bx*(ny/8) + by)*(nz/32) + bz and its
+ * 64 words are those of columns (8bx+u, 8by+v), u, v in [0, 8), word bz,
+ * u-major.  Needs nx, ny multiples of 8 and nz of 32 (else
+ * TV_ERR_UNSUPPORTED_DIMS); tv_brick_count_max gives the number of bricks
+ * (0 for such dims).  Writes the number of non-empty bricks to the device
+ * word `count`, and the first min(count, capacity) of them to ids[] and
+ * brick_words[] (64 words each, 16-byte aligned); capacity 0 only counts.
+ * `ws` (device) holds tv_bricks_workspace_bytes(dims) bytes of scratch.
+ */
+int64_t tv_brick_count_max(tv_dims dims);
+size_t tv_bricks_workspace_bytes(tv_dims dims);
+tv_status tv_bricks(const uint32_t *grid, tv_dims dims, uint32_t *ids, uint32_t *brick_words,
+                    int64_t capacity, uint32_t *count, void *ws, size_t ws_bytes, void *stream);
+
 /* Human-readable name of a status code (static storage). */
 const char *tv_status_string(tv_status s);
 

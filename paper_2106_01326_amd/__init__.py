@@ -42,7 +42,13 @@ EXPORTED = ("tv_grid_words", "tv_workspace_bytes", "tv_voxelize", "tv_voxelize_q
             "tv_fetch_status", "tv_status_string", "tv_last_error", "tv_profile_enable",
             "tv_profile_read", "tv_profile_stage_name", "tv_server_create", "tv_server_submit",
             "tv_server_poll", "tv_server_wait", "tv_server_result", "tv_server_copy_grid",
-            "tv_server_release", "tv_server_get_stats", "tv_server_destroy")
+            "tv_server_release", "tv_server_get_stats", "tv_server_destroy", "tv_unpack", "tv_pool",
+            "tv_brick_count_max", "tv_bricks_workspace_bytes", "tv_bricks")
+
+UNPACK_U8 = 0
+UNPACK_F32 = 1
+POOL_FRACTION = 0
+POOL_ANY = 1
 
 REQ_HOST_INPUTS = 0
 REQ_PINNED_INPUTS = 4
@@ -159,6 +165,16 @@ def load_library():
     lib.tv_profile_read.restype = st
     lib.tv_profile_stage_name.argtypes = [ctypes.c_int32]
     lib.tv_profile_stage_name.restype = ctypes.c_char_p
+    lib.tv_unpack.argtypes = [P, Dims, P, u32, P]
+    lib.tv_unpack.restype = st
+    lib.tv_pool.argtypes = [P, Dims, ctypes.c_int32, u32, P, P]
+    lib.tv_pool.restype = st
+    lib.tv_brick_count_max.argtypes = [Dims]
+    lib.tv_brick_count_max.restype = i64
+    lib.tv_bricks_workspace_bytes.argtypes = [Dims]
+    lib.tv_bricks_workspace_bytes.restype = ctypes.c_size_t
+    lib.tv_bricks.argtypes = [P, Dims, P, P, i64, P, P, ctypes.c_size_t, P]
+    lib.tv_bricks.restype = st
     _lib = lib
     return lib
 
@@ -286,6 +302,73 @@ def fetch_status(workspace, mesh_index: int = 0, stream=None) -> int:
     torch = _torch()
     wptr, _ = _dev_ptr(workspace, torch.uint8, None, "workspace")
     return int(lib.tv_fetch_status(wptr, int(mesh_index), _stream_handle(stream)))
+
+
+def _grid_ptr(grid, dims):
+    torch = _torch()
+    if not isinstance(grid, torch.Tensor) or not grid.is_cuda or grid.dtype not in (torch.int32, torch.uint32):
+        raise TypeError("grid must be a device int32/uint32 tensor")
+    if not grid.is_contiguous() or grid.numel() < grid_words(dims):
+        raise ValueError("grid must be contiguous with tv_grid_words(dims) words")
+    return ctypes.c_void_p(grid.data_ptr())
+
+
+def unpack(grid, dims, dtype=None, out=None, stream=None):
+    """Dense [nx, ny, nz] tensor of a packed grid (1 = set): uint8 by
+    default, or float32."""
+    lib = load_library()
+    torch = _torch()
+    dtype = dtype or torch.uint8
+    if dtype not in (torch.uint8, torch.float32):
+        raise TypeError("dtype must be uint8 or float32")
+    nx, ny, nz = (int(d) for d in dims)
+    if out is None:
+        out = torch.empty((nx, ny, nz), dtype=dtype, device=grid.device)
+    elif out.dtype != dtype or not out.is_contiguous() or out.numel() != nx * ny * nz:
+        raise ValueError("out must be a contiguous tensor of nx*ny*nz elements of dtype")
+    fmt = UNPACK_U8 if dtype == torch.uint8 else UNPACK_F32
+    _check(lib.tv_unpack(_grid_ptr(grid, dims), _dims(dims), ctypes.c_void_p(out.data_ptr()), fmt,
+                         _stream_handle(stream)))
+    return out
+
+
+def pool(grid, dims, factor, mode=POOL_FRACTION, out=None, stream=None):
+    """Coarser level by ``factor``: float32 [nx/f, ny/f, nz/f] occupancy
+    fractions (POOL_FRACTION) or the packed any-grid of dims/f (POOL_ANY)."""
+    lib = load_library()
+    torch = _torch()
+    f = int(factor)
+    nx, ny, nz = (int(d) for d in dims)
+    if out is None:
+        if mode == POOL_FRACTION:
+            out = torch.empty((nx // f, ny // f, nz // f), dtype=torch.float32, device=grid.device)
+        else:
+            out = torch.empty(grid_words((max(nx // f, 1), max(ny // f, 1), max(nz // f, 1))),
+                              dtype=torch.int32, device=grid.device)
+    _check(lib.tv_pool(_grid_ptr(grid, dims), _dims(dims), f, int(mode), ctypes.c_void_p(out.data_ptr()),
+                       _stream_handle(stream)))
+    return out
+
+
+def bricks(grid, dims, capacity=None, stream=None):
+    """Non-empty 8x8x32 bricks of a grid in increasing id: (ids uint32 [n],
+    words uint32 [n, 64]) as device tensors (synchronizes to read n)."""
+    lib = load_library()
+    torch = _torch()
+    nmax = int(lib.tv_brick_count_max(_dims(dims)))
+    cap = nmax if capacity is None else int(capacity)
+    dev = grid.device
+    ids = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+    words = torch.empty((max(cap, 1), 64), dtype=torch.int32, device=dev)
+    count = torch.zeros(1, dtype=torch.int32, device=dev)
+    wsb = int(lib.tv_bricks_workspace_bytes(_dims(dims)))
+    ws = alloc_workspace(wsb, dev)
+    _check(lib.tv_bricks(_grid_ptr(grid, dims), _dims(dims), ctypes.c_void_p(ids.data_ptr()),
+                         ctypes.c_void_p(words.data_ptr()), cap, ctypes.c_void_p(count.data_ptr()),
+                         ctypes.c_void_p(ws.data_ptr()), wsb, _stream_handle(stream)))
+    n = int(count.item())
+    k = min(n, cap)
+    return ids[:k], words[:k], n
 
 
 def profile_enable(on: bool = True):
