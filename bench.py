@@ -378,6 +378,85 @@ def bench_grids(args, torch, tv):
     print(json.dumps(res), flush=True)
 
 
+QUALITY_OPS_PER_TET = 6 * 60 + 20  # six dihedral angles (cross products, norms, sqrt, acos) + exact 6V
+
+
+def bench_quality(args, torch, tv):
+    """Mesh files and the quality report.  The timed step is one
+    tv_mesh_quality call on the large mesh (snap, per-tet report with exact
+    voxel coverage, grid popcount, readback); the native readers' throughput
+    on a written medium mesh is reported alongside."""
+    import tempfile
+
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from meshfiles import write_gmsh22, write_gmsh41, write_medit
+
+    log("generating workload large")
+    m = make_workload("large")
+    dev = torch.device("cuda:0")
+    v = torch.from_numpy(m.verts).to(dev)
+    t = torch.from_numpy(m.tets).to(dev)
+    grid, _ = tv.voxelize(v, t, m.dims, m.bbox)
+    ws = tv.alloc_workspace(tv.load_library().tv_quality_workspace_bytes(m.nv), dev)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        tv.quality(v, t, m.dims, m.bbox, grid, workspace=ws)
+    tv.profile_read()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        rep = tv.quality(v, t, m.dims, m.bbox, grid, workspace=ws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    q_lat = tv.snap(v, m.bbox).cpu().numpy()
+    n_nonempty, n_cols, _ = candidate_work(q_lat, m.tets, m.dims)
+    ops = QUALITY_OPS_PER_TET * m.nt + SETUP_OPS_PER_TET * n_nonempty + OPS_PER_COLUMN * n_cols
+    achieved = ops / (ms * 1e-3) / 1e12
+    log(f"quality: {ms:.3f} ms per report; {rep}")
+    # readers
+    mm = make_workload("medium")
+    verts = mm.qverts.astype(np.float32) / np.float32(65536.0) if mm.verts is None else mm.verts
+    readers = {}
+    cpu = None
+    with tempfile.TemporaryDirectory() as d:
+        files = {"medit": os.path.join(d, "m.mesh"), "gmsh22": os.path.join(d, "m22.msh"),
+                 "gmsh41": os.path.join(d, "m41.msh")}
+        write_medit(files["medit"], verts, mm.tets)
+        write_gmsh22(files["gmsh22"], verts, mm.tets)
+        write_gmsh41(files["gmsh41"], verts, mm.tets)
+        for k, f in files.items():
+            size = os.path.getsize(f)
+            t0 = time.perf_counter()
+            rv, rt, _, _ = tv.read_mesh(f)
+            dt = time.perf_counter() - t0
+            readers[k] = {"MB": size / 1e6, "s": dt, "MB_per_s": size / 1e6 / dt, "tets": int(rt.shape[0]),
+                          "exact": bool(np.array_equal(rv, verts) and np.array_equal(rt, mm.tets))}
+        log(f"readers {readers}")
+        if not args.no_cpu_baseline:
+            import oracle.meshio as M
+
+            size = os.path.getsize(files["medit"])
+            t0 = time.perf_counter()
+            ov, ot, _ = M.read_mesh(files["medit"])
+            dt = time.perf_counter() - t0
+            cpu = {"value": size / 1e6 / dt, "unit": "MB/s (MEDIT parse)", "cores": 1, "kind": "oracle",
+                   "sample": f"the medium mesh as a {size / 1e6:.0f} MB MEDIT file ({dt:.1f} s)",
+                   "native_MB_per_s": readers["medit"]["MB_per_s"],
+                   "identical": bool(np.array_equal(ov, verts) and np.array_equal(ot, mm.tets))}
+    res = {"metric": "tets quality-checked/s", "value": m.nt / (ms * 1e-3), "unit": "tets/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic (seeded jittered Kuhn meshes)",
+           "config": {"workload": "quality report of the large mesh; readers on the medium mesh",
+                      "tets": m.nt, "grid": list(m.dims)},
+           "roofline": {"bound": "alu", "kernel": "k_quality", "achieved": achieved, "peak": VALU_PEAK_TOPS,
+                        "unit": "TOP/s", "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
+                        "ops_per_launch": ops, "note": "timed step includes snap, popcount and readback"},
+           "report": rep, "readers": readers, "cpu_baseline": cpu}
+    print(json.dumps(res), flush=True)
+
+
 def cpu_baseline_batch(meshes, batch, target_s):
     """The oracle on the first meshes of the batch until about target_s of
     wall time; compared bit for bit with the batched GPU grids."""
@@ -407,7 +486,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="large",
-                    choices=["large", "medium", "small", "batch", "serving", "grids"])
+                    choices=["large", "medium", "small", "batch", "serving", "grids", "quality"])
     ap.add_argument("--requests", type=int, default=10000)
     ap.add_argument("--batch-meshes", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -444,6 +523,8 @@ def main():
         return bench_serving(args, torch, tv)
     if args.workload == "grids":
         return bench_grids(args, torch, tv)
+    if args.workload == "quality":
+        return bench_quality(args, torch, tv)
     log(f"generating workload {args.workload}")
     t0 = time.perf_counter()
     m = make_workload(args.workload)

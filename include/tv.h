@@ -68,6 +68,7 @@ typedef int32_t tv_status;
 #define TV_ERR_TOO_LARGE (-8)        /* request larger than the server's memory */
 #define TV_ERR_TIMEOUT (-9)          /* wait timed out */
 #define TV_ERR_NOT_FOUND (-10)       /* unknown ticket, or result asked before completion */
+#define TV_ERR_IO (-11)              /* a mesh file that cannot be read or parsed */
 
 #define TV_Q_MIN (-16384)        /* lattice range: [-2^14, 2^16 + 2^14] per axis */
 #define TV_Q_MAX (65536 + 16384)
@@ -299,6 +300,67 @@ int64_t tv_brick_count_max(tv_dims dims);
 size_t tv_bricks_workspace_bytes(tv_dims dims);
 tv_status tv_bricks(const uint32_t *grid, tv_dims dims, uint32_t *ids, uint32_t *brick_words,
                     int64_t capacity, uint32_t *count, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Tet-mesh files (host side; the step before voxelization: the paper's
+ * pipeline voxelizes the tetrahedral meshes its mesher writes, Section 3).
+ * tv_read_mesh parses a MEDIT ".mesh" (ASCII; Dimension 3, sections
+ * Vertices and Tetrahedra, other known sections skipped) or a Gmsh ".msh"
+ * file (ASCII, format 2.2 or 4.1; 4-node tetrahedra, other element types
+ * skipped), detected from the file's first token.  Coordinates are parsed as
+ * double and rounded to float; tet indices become 0-based.  On success the
+ * library allocates `verts` [nv][3] and `tets` [nt][4] in host memory (free
+ * them with tv_free_host_mesh) and sets bbox to the vertices' min/max.
+ * Errors: TV_ERR_INVALID_ARG, TV_ERR_IO (unreadable, malformed, binary or
+ * unsupported content, an index to an unknown vertex); nothing is allocated
+ * then.
+ */
+typedef struct {
+    float *verts;               /* [nv][3] */
+    int64_t nv;
+    int32_t *tets;              /* [nt][4], 0-based */
+    int64_t nt;
+    tv_bbox bbox;               /* min / max of the vertices */
+    int64_t skipped_elements;   /* elements that are not 4-node tetrahedra */
+} tv_host_mesh;
+tv_status tv_read_mesh(const char *path, tv_host_mesh *out);
+void tv_free_host_mesh(tv_host_mesh *m);
+
+/*
+ * Mesh quality report: the assumptions the paper's voxelizer makes about its
+ * input (Section 3, "Voxelization": a large minimum angle, no overlapping
+ * tets, small variance), measured on the voxelizer's own lattice.  Inputs
+ * as for tv_voxelize (vert_format TV_VERTS_F32 with bbox, or TV_VERTS_Q32
+ * lattice coordinates, in which case bbox only scales lattice units to
+ * world units), plus `grid`: the grid of these tets at `dims` (device; e.g.
+ * what tv_voxelize wrote).  `flags` may hold TV_TIE_STRICT.  Blocking: it
+ * synchronizes `stream` and fills the host struct `out`.
+ *   tets / invalid: tets examined / skipped for an index outside [0, nv) or
+ *     a vertex that fails to snap (or lies off the lattice range);
+ *   degenerate / inverted: 6V == 0 / 6V < 0 on the lattice (exact);
+ *   min_dihedral_deg, mean_min_dihedral_deg, min_dihedral_below[k]: over
+ *     non-degenerate tets, the smallest of a tet's six dihedral angles in
+ *     world coordinates (degrees): its minimum, its mean, and how many tets
+ *     have it below 1, 5, 10 and 20 degrees;
+ *   volume_mean, volume_cv: mean and coefficient of variation (std / mean)
+ *     of the non-degenerate tets' volumes (world units);
+ *   covered_voxels: the sum over tets of the voxel centers each contains
+ *     under the voxelizer's rule; occupied_voxels: set voxels of `grid`.
+ *     Without overlapping tets the two are equal (exactly, under the
+ *     half-open rule); covered - occupied counts the extra coverage.
+ * `ws` (device, 256-byte aligned) holds tv_quality_workspace_bytes(nv).
+ */
+typedef struct {
+    int64_t tets, invalid, degenerate, inverted;
+    int64_t min_dihedral_below[4]; /* below 1, 5, 10, 20 degrees */
+    double min_dihedral_deg, mean_min_dihedral_deg;
+    double volume_mean, volume_cv;
+    int64_t covered_voxels, occupied_voxels;
+} tv_quality;
+size_t tv_quality_workspace_bytes(int64_t nv);
+tv_status tv_mesh_quality(const void *verts, uint32_t vert_format, int64_t nv, const int32_t *tets,
+                          int64_t nt, tv_dims dims, tv_bbox bbox, const uint32_t *grid, uint32_t flags,
+                          void *ws, size_t ws_bytes, void *stream, tv_quality *out);
 
 /* Human-readable name of a status code (static storage). */
 const char *tv_status_string(tv_status s);

@@ -28,6 +28,7 @@ TV_ERR_HIP = -7
 TV_ERR_TOO_LARGE = -8
 TV_ERR_TIMEOUT = -9
 TV_ERR_NOT_FOUND = -10
+TV_ERR_IO = -11
 
 TIE_HALF_OPEN = 0
 TIE_STRICT = 1
@@ -43,7 +44,8 @@ EXPORTED = ("tv_grid_words", "tv_workspace_bytes", "tv_voxelize", "tv_voxelize_q
             "tv_profile_read", "tv_profile_stage_name", "tv_server_create", "tv_server_submit",
             "tv_server_poll", "tv_server_wait", "tv_server_result", "tv_server_copy_grid",
             "tv_server_release", "tv_server_get_stats", "tv_server_destroy", "tv_unpack", "tv_pool",
-            "tv_brick_count_max", "tv_bricks_workspace_bytes", "tv_bricks")
+            "tv_brick_count_max", "tv_bricks_workspace_bytes", "tv_bricks", "tv_read_mesh",
+            "tv_free_host_mesh", "tv_quality_workspace_bytes", "tv_mesh_quality")
 
 UNPACK_U8 = 0
 UNPACK_F32 = 1
@@ -68,6 +70,19 @@ class MeshC(ctypes.Structure):
     _fields_ = [("verts", ctypes.c_void_p), ("vert_format", ctypes.c_uint32), ("nv", ctypes.c_int64),
                 ("tets", ctypes.c_void_p), ("nt", ctypes.c_int64), ("dims", Dims), ("bbox", BBox),
                 ("grid", ctypes.c_void_p)]
+
+
+class HostMeshC(ctypes.Structure):
+    _fields_ = [("verts", ctypes.c_void_p), ("nv", ctypes.c_int64), ("tets", ctypes.c_void_p),
+                ("nt", ctypes.c_int64), ("bbox", BBox), ("skipped_elements", ctypes.c_int64)]
+
+
+class QualityC(ctypes.Structure):
+    _fields_ = [("tets", ctypes.c_int64), ("invalid", ctypes.c_int64), ("degenerate", ctypes.c_int64),
+                ("inverted", ctypes.c_int64), ("min_dihedral_below", ctypes.c_int64 * 4),
+                ("min_dihedral_deg", ctypes.c_double), ("mean_min_dihedral_deg", ctypes.c_double),
+                ("volume_mean", ctypes.c_double), ("volume_cv", ctypes.c_double),
+                ("covered_voxels", ctypes.c_int64), ("occupied_voxels", ctypes.c_int64)]
 
 
 class RequestC(ctypes.Structure):
@@ -165,6 +180,14 @@ def load_library():
     lib.tv_profile_read.restype = st
     lib.tv_profile_stage_name.argtypes = [ctypes.c_int32]
     lib.tv_profile_stage_name.restype = ctypes.c_char_p
+    lib.tv_read_mesh.argtypes = [ctypes.c_char_p, P]
+    lib.tv_read_mesh.restype = st
+    lib.tv_free_host_mesh.argtypes = [P]
+    lib.tv_free_host_mesh.restype = None
+    lib.tv_quality_workspace_bytes.argtypes = [i64]
+    lib.tv_quality_workspace_bytes.restype = ctypes.c_size_t
+    lib.tv_mesh_quality.argtypes = [P, u32, i64, P, i64, Dims, BBox, P, u32, P, ctypes.c_size_t, P, P]
+    lib.tv_mesh_quality.restype = st
     lib.tv_unpack.argtypes = [P, Dims, P, u32, P]
     lib.tv_unpack.restype = st
     lib.tv_pool.argtypes = [P, Dims, ctypes.c_int32, u32, P, P]
@@ -302,6 +325,49 @@ def fetch_status(workspace, mesh_index: int = 0, stream=None) -> int:
     torch = _torch()
     wptr, _ = _dev_ptr(workspace, torch.uint8, None, "workspace")
     return int(lib.tv_fetch_status(wptr, int(mesh_index), _stream_handle(stream)))
+
+
+def read_mesh(path):
+    """Read a MEDIT .mesh or Gmsh .msh (ASCII) tet mesh with the native reader:
+    (verts float32 [nv, 3], tets int32 [nt, 4] 0-based, bbox ((lo), (hi)),
+    skipped non-tet elements), as host numpy arrays."""
+    import numpy as np
+
+    lib = load_library()
+    m = HostMeshC()
+    _check(lib.tv_read_mesh(os.fsencode(path), ctypes.byref(m)))
+    try:
+        verts = np.ctypeslib.as_array(ctypes.cast(m.verts, ctypes.POINTER(ctypes.c_float)),
+                                      shape=(m.nv * 3,)).reshape(m.nv, 3).copy() if m.nv else \
+            np.zeros((0, 3), np.float32)
+        tets = np.ctypeslib.as_array(ctypes.cast(m.tets, ctypes.POINTER(ctypes.c_int32)),
+                                     shape=(m.nt * 4,)).reshape(m.nt, 4).copy() if m.nt else \
+            np.zeros((0, 4), np.int32)
+        bbox = (tuple(m.bbox.lo), tuple(m.bbox.hi))
+        return verts, tets, bbox, int(m.skipped_elements)
+    finally:
+        lib.tv_free_host_mesh(ctypes.byref(m))
+
+
+def quality(verts, tets, dims, bbox, grid, *, qverts=False, strict=False, workspace=None, stream=None):
+    """Mesh quality report (see tv_mesh_quality): a dict of the counts,
+    dihedral-angle and volume statistics, and covered vs occupied voxels of
+    ``grid`` (the grid of these tets at ``dims``).  Synchronizes."""
+    lib = load_library()
+    torch = _torch()
+    vptr, nv = _dev_ptr(verts, torch.int32 if qverts else torch.float32, 3, "verts")
+    tptr, nt = _dev_ptr(tets, torch.int32, 4, "tets")
+    need = int(lib.tv_quality_workspace_bytes(nv))
+    if workspace is None:
+        workspace = alloc_workspace(need, verts.device)
+    wptr, _ = _dev_ptr(workspace, torch.uint8, None, "workspace")
+    out = QualityC()
+    _check(lib.tv_mesh_quality(vptr, VERTS_Q32 if qverts else VERTS_F32, nv, tptr, nt, _dims(dims),
+                               _bbox(bbox), _grid_ptr(grid, dims), TIE_STRICT if strict else 0, wptr,
+                               workspace.numel(), _stream_handle(stream), ctypes.byref(out)))
+    r = {k: getattr(out, k) for k, _ in QualityC._fields_}
+    r["min_dihedral_below"] = list(out.min_dihedral_below)
+    return r
 
 
 def _grid_ptr(grid, dims):

@@ -373,6 +373,10 @@ const char *tv_status_string(tv_status s) {
     case TV_ERR_RANGE: return "TV_ERR_RANGE";
     case TV_ERR_WORKSPACE: return "TV_ERR_WORKSPACE";
     case TV_ERR_HIP: return "TV_ERR_HIP";
+    case TV_ERR_TOO_LARGE: return "TV_ERR_TOO_LARGE";
+    case TV_ERR_TIMEOUT: return "TV_ERR_TIMEOUT";
+    case TV_ERR_NOT_FOUND: return "TV_ERR_NOT_FOUND";
+    case TV_ERR_IO: return "TV_ERR_IO";
     default: return "TV_ERR_UNKNOWN";
     }
 }

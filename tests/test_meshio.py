@@ -1,0 +1,93 @@
+"""Tet-mesh file readers: the oracle parser pinned by hand-written fixtures
+(the unit cube's 6 Kuhn tets in each format), and the library's native
+reader bit-identical to it on the fixtures and on written synthetic meshes.
+Host code only: no GPU."""
+import os
+
+import numpy as np
+import pytest
+
+from meshfiles import write_gmsh22, write_gmsh41, write_medit
+from paper_2106_01326_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+FIXTURES = {"cube_kuhn.mesh": 2, "cube_kuhn_v22.msh": 2, "cube_kuhn_v41.msh": 1}  # skipped elements
+
+# corner (i, j, k) is vertex i + 2j + 4k; one tet per ordering of the axes
+CUBE_VERTS = np.array([[i & 1, (i >> 1) & 1, (i >> 2) & 1] for i in range(8)], np.float32)
+CUBE_TETS = np.array([[0, 1, 3, 7], [0, 1, 5, 7], [0, 2, 3, 7], [0, 2, 6, 7], [0, 4, 5, 7], [0, 4, 6, 7]],
+                     np.int32)
+
+
+@pytest.mark.parametrize("name", sorted(FIXTURES))
+def test_oracle_parser_reads_the_cube_fixtures(name):
+    import oracle.meshio as M
+
+    v, t, skipped = M.read_mesh(os.path.join(GOLDEN, name))
+    assert v.dtype == np.float32 and t.dtype == np.int32
+    assert np.array_equal(v, CUBE_VERTS) and np.array_equal(t, CUBE_TETS)
+    assert skipped == FIXTURES[name]
+    # the six Kuhn tets fill the unit cube: |det| = 1 each, total volume 1
+    P = v[t].astype(np.float64)
+    dets = np.linalg.det(P[:, 1:] - P[:, :1])
+    assert np.allclose(np.abs(dets), 1.0) and np.isclose(np.abs(dets).sum() / 6.0, 1.0)
+
+
+@pytest.mark.parametrize("name", sorted(FIXTURES))
+def test_native_reader_matches_on_fixtures(name):
+    import oracle.meshio as M
+    import paper_2106_01326_amd as tv
+
+    path = os.path.join(GOLDEN, name)
+    v, t, bbox, skipped = tv.read_mesh(path)
+    ov, ot, osk = M.read_mesh(path)
+    assert np.array_equal(v, ov) and np.array_equal(t, ot) and skipped == osk
+    assert bbox == ((0.0, 0.0, 0.0), (1.0, 1.0, 1.0))
+
+
+@pytest.mark.parametrize("fmt", ["medit", "gmsh22", "gmsh41"])
+def test_written_meshes_round_trip(tmp_path, fmt):
+    import oracle.meshio as M
+    import paper_2106_01326_amd as tv
+
+    m = synth.make_mesh(10, 0.4, 64, "ellipsoids", 3, 3001)
+    path = str(tmp_path / f"m.{'mesh' if fmt == 'medit' else 'msh'}")
+    if fmt == "medit":
+        write_medit(path, m.verts, m.tets)
+    elif fmt == "gmsh22":
+        write_gmsh22(path, m.verts, m.tets, tag0=100)
+    else:
+        write_gmsh41(path, m.verts, m.tets, block=777)
+    v, t, bbox, skipped = tv.read_mesh(path)
+    ov, ot, osk = M.read_mesh(path)
+    assert np.array_equal(v, m.verts) and np.array_equal(t, m.tets)
+    assert np.array_equal(ov, m.verts) and np.array_equal(ot, m.tets)
+    assert skipped == osk == (1 if fmt == "gmsh22" else 0)
+    assert bbox == (tuple(m.verts.min(0).tolist()), tuple(m.verts.max(0).tolist()))
+
+
+BAD = {
+    "dim2.mesh": "MeshVersionFormatted 2\nDimension 2\nEnd\n",
+    "keyword.mesh": "MeshVersionFormatted 2\nDimension 3\nBogus 1\n1\nEnd\n",
+    "truncated.mesh": "MeshVersionFormatted 2\nDimension 3\nVertices\n2\n0 0 0 0\n",
+    "index.mesh": "MeshVersionFormatted 2\nDimension 3\nVertices\n1\n0 0 0 0\nTetrahedra\n1\n1 1 1 2 0\nEnd\n",
+    "binary.msh": "$MeshFormat\n4.1 1 8\n$EndMeshFormat\n",
+    "version.msh": "$MeshFormat\n3.0 0 8\n$EndMeshFormat\n",
+    "node.msh": "$MeshFormat\n2.2 0 8\n$EndMeshFormat\n$Nodes\n1\n1 0 0 0\n$EndNodes\n"
+                "$Elements\n1\n1 4 0 1 1 1 9\n$EndElements\n",
+    "unknown.txt": "hello\n",
+}
+
+
+@pytest.mark.parametrize("name", sorted(BAD))
+def test_native_reader_errors(tmp_path, name):
+    import paper_2106_01326_amd as tv
+
+    p = tmp_path / name
+    p.write_text(BAD[name])
+    with pytest.raises(tv.TVError) as e:
+        tv.read_mesh(str(p))
+    assert e.value.code == tv.TV_ERR_IO
+    with pytest.raises(tv.TVError) as e:
+        tv.read_mesh(str(tmp_path / "missing.mesh"))
+    assert e.value.code == tv.TV_ERR_IO
