@@ -78,6 +78,10 @@ typedef int32_t tv_status;
 #define TV_TIE_STRICT 1u    /* Theorem 1 literally: a center on a face is outside */
 #define TV_PATH_PER_TET 2u  /* reference path: one lane per tet, word atomics into a
                                cleared grid (same output, slower; for A/B checks) */
+#define TV_ACCUMULATE 8u    /* OR the voxels into the grid instead of overwriting it (the
+                               grid must hold a previous result or zeros), and keep the
+                               data-error status words of earlier calls on this workspace:
+                               voxelizing a mesh in several tet subsets gives its grid */
 
 typedef struct {
     int32_t nx, ny, nz; /* each a power of two in [1, 32768] */
@@ -251,6 +255,26 @@ tv_status tv_server_release(tv_server *s, int64_t ticket);
 tv_status tv_server_get_stats(tv_server *s, tv_server_stats *out);
 /* Waits for in-flight waves, stops the threads and frees everything. */
 tv_status tv_server_destroy(tv_server *s);
+
+/*
+ * Voxelization from host inputs with the copies overlapped (the transfer
+ * cost of Table 1's CPU+GPU column): the vertices, then the tets in `chunks`
+ * consecutive slices, are copied on `copy_stream` into the caller's device
+ * buffers verts_dev [nv][3] and tets_dev [nt][4]; on `stream`, slice k is
+ * voxelized as soon as it has arrived (slice 0 overwrites the grid, later
+ * slices use TV_ACCUMULATE), so copying slice k+1 overlaps voxelizing slice
+ * k.  The grid equals tv_voxelize's on the whole mesh.  Host inputs should
+ * be pinned for the copies to run asynchronously.  `ws` needs
+ * tv_workspace_bytes(nv, ceil(nt / chunks), dims, flags) bytes.  chunks is
+ * clamped to [1, 64]; every slice repeats the launch sequence (and the snap
+ * of all vertices), so slices of about a million tets or more pay off.
+ * Returns after enqueueing; `stream` orders after all the copies.  flags:
+ * TV_TIE_STRICT, TV_PATH_PER_TET.
+ */
+tv_status tv_voxelize_pipelined(const float *verts_host, int64_t nv, const int32_t *tets_host,
+                                int64_t nt, tv_dims dims, tv_bbox bbox, float *verts_dev,
+                                int32_t *tets_dev, uint32_t *grid, void *ws, size_t ws_bytes,
+                                void *stream, void *copy_stream, int32_t chunks, uint32_t flags);
 
 /*
  * Grid consumers (device-side, asynchronous on `stream`, allocate nothing).

@@ -32,6 +32,7 @@ TV_ERR_IO = -11
 
 TIE_HALF_OPEN = 0
 TIE_STRICT = 1
+ACCUMULATE = 8
 PATH_PER_TET = 2
 Q_INVALID = -(1 << 31)
 
@@ -45,7 +46,8 @@ EXPORTED = ("tv_grid_words", "tv_workspace_bytes", "tv_voxelize", "tv_voxelize_q
             "tv_server_poll", "tv_server_wait", "tv_server_result", "tv_server_copy_grid",
             "tv_server_release", "tv_server_get_stats", "tv_server_destroy", "tv_unpack", "tv_pool",
             "tv_brick_count_max", "tv_bricks_workspace_bytes", "tv_bricks", "tv_read_mesh",
-            "tv_free_host_mesh", "tv_quality_workspace_bytes", "tv_mesh_quality")
+            "tv_free_host_mesh", "tv_quality_workspace_bytes", "tv_mesh_quality",
+            "tv_voxelize_pipelined")
 
 UNPACK_U8 = 0
 UNPACK_F32 = 1
@@ -184,6 +186,9 @@ def load_library():
     lib.tv_read_mesh.restype = st
     lib.tv_free_host_mesh.argtypes = [P]
     lib.tv_free_host_mesh.restype = None
+    lib.tv_voxelize_pipelined.argtypes = [P, i64, P, i64, Dims, BBox, P, P, P, P, ctypes.c_size_t, P, P,
+                                          ctypes.c_int32, u32]
+    lib.tv_voxelize_pipelined.restype = st
     lib.tv_quality_workspace_bytes.argtypes = [i64]
     lib.tv_quality_workspace_bytes.restype = ctypes.c_size_t
     lib.tv_mesh_quality.argtypes = [P, u32, i64, P, i64, Dims, BBox, P, u32, P, ctypes.c_size_t, P, P]
@@ -271,19 +276,23 @@ def _bbox(bbox) -> BBox:
 
 
 def voxelize(verts, tets, dims, bbox=None, *, qverts=False, strict=False, per_tet=False, grid=None,
-             workspace=None, stream=None):
+             workspace=None, stream=None, accumulate=False):
     """Voxelize one mesh on the GPU (asynchronous on ``stream``).
 
     verts: [nv,3] float32 world coordinates (``qverts=False``, needs ``bbox``
     = (lo[3], hi[3])) or [nv,3] int32 lattice coordinates (``qverts=True``).
-    tets: [nt,4] int32.  ``per_tet`` selects the reference path.  Returns
+    tets: [nt,4] int32.  ``per_tet`` selects the reference path.
+    ``accumulate`` ORs into ``grid`` instead of overwriting it.  Returns
     (grid, workspace); call ``fetch_status`` on the workspace to read
     device-side data errors.
     """
     lib = load_library()
     torch = _torch()
     d = _dims(dims)
-    flags = (TIE_STRICT if strict else TIE_HALF_OPEN) | (PATH_PER_TET if per_tet else 0)
+    flags = (TIE_STRICT if strict else TIE_HALF_OPEN) | (PATH_PER_TET if per_tet else 0) | \
+        (ACCUMULATE if accumulate else 0)
+    if accumulate and grid is None:
+        raise ValueError("accumulate needs the grid to add to")
     vptr, nv = _dev_ptr(verts, torch.int32 if qverts else torch.float32, 3, "verts")
     tptr, nt = _dev_ptr(tets, torch.int32, 4, "tets")
     if grid is None:
@@ -304,6 +313,38 @@ def voxelize(verts, tets, dims, bbox=None, *, qverts=False, strict=False, per_te
         rc = lib.tv_voxelize(vptr, nv, tptr, nt, d, _bbox(bbox), gptr, wptr, workspace.numel(), s, flags)
     _check(rc)
     return grid, workspace
+
+
+def voxelize_pipelined(verts_host, tets_host, dims, bbox, chunks=8, *, strict=False, per_tet=False,
+                       verts_dev=None, tets_dev=None, grid=None, workspace=None, stream=None,
+                       copy_stream=None):
+    """Voxelize host inputs (pinned CPU tensors for overlap) with the copies
+    of tet slices overlapped with the voxelization of earlier slices; returns
+    (grid, workspace, verts_dev, tets_dev).  ``copy_stream`` defaults to a
+    new torch stream."""
+    lib = load_library()
+    torch = _torch()
+    for t, dt, w, name in ((verts_host, torch.float32, 3, "verts_host"), (tets_host, torch.int32, 4, "tets_host")):
+        if not isinstance(t, torch.Tensor) or t.is_cuda or t.dtype != dt or t.dim() != 2 or t.shape[1] != w \
+                or not t.is_contiguous():
+            raise TypeError(f"{name} must be a contiguous host {dt} tensor of shape [n, {w}]")
+    nv, nt = int(verts_host.shape[0]), int(tets_host.shape[0])
+    dev = torch.device("cuda", torch.cuda.current_device())
+    verts_dev = torch.empty((nv, 3), dtype=torch.float32, device=dev) if verts_dev is None else verts_dev
+    tets_dev = torch.empty((nt, 4), dtype=torch.int32, device=dev) if tets_dev is None else tets_dev
+    grid = alloc_grid(dims, dev) if grid is None else grid
+    k = max(1, min(int(chunks), 64))
+    per = (nt + k - 1) // k if nt else 0
+    flags = (TIE_STRICT if strict else TIE_HALF_OPEN) | (PATH_PER_TET if per_tet else 0)
+    if workspace is None:
+        workspace = alloc_workspace(workspace_bytes(nv, per, dims, flags), dev)
+    copy_stream = copy_stream if copy_stream is not None else torch.cuda.Stream()
+    _check(lib.tv_voxelize_pipelined(
+        ctypes.c_void_p(verts_host.data_ptr()), nv, ctypes.c_void_p(tets_host.data_ptr()), nt, _dims(dims),
+        _bbox(bbox), ctypes.c_void_p(verts_dev.data_ptr()), ctypes.c_void_p(tets_dev.data_ptr()),
+        ctypes.c_void_p(grid.data_ptr()), ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+        _stream_handle(stream), ctypes.c_void_p(copy_stream.cuda_stream), k, flags))
+    return grid, workspace, verts_dev, tets_dev
 
 
 def snap(verts, bbox, out=None, stream=None):

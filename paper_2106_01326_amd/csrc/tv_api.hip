@@ -67,7 +67,7 @@ int device_cus() {
     return cached[dev];
 }
 
-constexpr uint32_t kKnownFlags = TV_TIE_STRICT | TV_PATH_PER_TET;
+constexpr uint32_t kKnownFlags = TV_TIE_STRICT | TV_PATH_PER_TET | TV_ACCUMULATE;
 constexpr int64_t kMaxTets = (int64_t)1 << 28;  // piece slots stay below 2^32
 
 // Host-visible checks of one mesh; `which` prefixes messages of batch entries.
@@ -146,6 +146,8 @@ tv_status run_impl(std::vector<tv::MeshDesc> &descs, const tv::CallSizes &c, uin
     T.chunk = tv::kChunkPieces;
     T.strip = tv::kStripColumns;
     T.piece_cap = tv::kPieceCap;
+    const bool accumulate = (flags & TV_ACCUMULATE) != 0;
+    T.accumulate = accumulate ? 1 : 0;
     T.nv_total = c.nv;
     T.nt_total = c.nt;
     T.ntiles_total = c.ntiles;
@@ -174,7 +176,13 @@ tv_status run_impl(std::vector<tv::MeshDesc> &descs, const tv::CallSizes &c, uin
     tv::profile_count_call();
     {
         tv::StageScope sc(tv::kStageClear, s);
-        tv::launch_clear(b.meta, (int64_t)L.clear_end / 4, s);
+        if (!accumulate) {
+            tv::launch_clear(b.meta, (int64_t)L.clear_end / 4, s);
+        } else {
+            // keep the status words: data errors of earlier accumulated calls stay visible
+            tv::launch_clear(b.meta, tv::kMetaWords, s);
+            tv::launch_clear(b.tile_count, (int64_t)(L.clear_end - L.tile_count) / 4, s);
+        }
         tv::launch_set_word(b.meta + tv::kMetaMeshes, (uint32_t)c.meshes, s);
     }
     {
@@ -186,7 +194,7 @@ tv_status run_impl(std::vector<tv::MeshDesc> &descs, const tv::CallSizes &c, uin
     if (flags & TV_PATH_PER_TET) {
         tv::StageScope sc(tv::kStageVoxelize, s);
         for (const tv::MeshDesc &d : descs) {
-            tv::launch_clear(d.grid, (int64_t)d.g.n[0] * d.g.n[1] * d.g.words, s);
+            if (!accumulate) tv::launch_clear(d.grid, (int64_t)d.g.n[0] * d.g.n[1] * d.g.words, s);
             tv::launch_voxelize_per_tet(d, b, strict, s);
         }
         return check_hip("per-tet voxelize launch");
@@ -196,7 +204,7 @@ tv_status run_impl(std::vector<tv::MeshDesc> &descs, const tv::CallSizes &c, uin
         tv::launch_bin_count(T, b, s);
         tv::launch_scan_tiles(T, b, s);
         tv::launch_bin_scatter(T, b, s);
-        tv::launch_zero_shared_tiles(T, b, s);
+        if (!accumulate) tv::launch_zero_shared_tiles(T, b, s);
     }
     if ((st = check_hip("binning launch"))) return st;
     const int cus = device_cus();
@@ -327,6 +335,55 @@ tv_status tv_voxelize_batch(const tv_mesh *meshes, int32_t n, void *ws, size_t w
     if (c.nt > kMaxTets) return fail(TV_ERR_INVALID_ARG, "batch has more than 2^28 tets");
     if ((st = check_ws(ws, ws_bytes, tv::layout(c).total, flags))) return st;
     return run_impl(descs, c, static_cast<uint8_t *>(ws), reinterpret_cast<hipStream_t>(stream), flags);
+}
+
+tv_status tv_voxelize_pipelined(const float *verts_host, int64_t nv, const int32_t *tets_host,
+                                int64_t nt, tv_dims dims, tv_bbox bbox, float *verts_dev,
+                                int32_t *tets_dev, uint32_t *grid, void *ws, size_t ws_bytes,
+                                void *stream, void *copy_stream, int32_t chunks, uint32_t flags) {
+    if ((flags & TV_ACCUMULATE) || (flags & ~kKnownFlags))
+        return fail(TV_ERR_INVALID_ARG, "bad flags 0x%x for a pipelined call", flags);
+    if (nv < 0 || nt < 0 || (nv && (!verts_host || !verts_dev)) || (nt && (!tets_host || !tets_dev)))
+        return fail(TV_ERR_INVALID_ARG, "null or negative pipelined inputs");
+    const int64_t k = chunks < 1 ? 1 : (chunks > 64 ? 64 : chunks);
+    const int64_t per = nt ? (nt + k - 1) / k : 0;
+    const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const hipStream_t cs = reinterpret_cast<hipStream_t>(copy_stream);
+    // host checks of the whole call before anything is enqueued
+    tv_status st = check_mesh_impl(verts_dev, TV_VERTS_F32, nv, tets_dev, nt, dims, &bbox, grid, "");
+    if (st) return st;
+    if ((st = check_ws(ws, ws_bytes, tv_workspace_bytes(nv, per, dims, flags), flags))) return st;
+    const int64_t nslices = per ? (nt + per - 1) / per : 1;
+    std::vector<hipEvent_t> ev((size_t)nslices + 1, nullptr);
+    for (auto &e : ev)
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+            for (auto &x : ev)
+                if (x) hipEventDestroy(x);
+            return fail(TV_ERR_HIP, "event creation failed");
+        }
+    bool ok = true;
+    if (nv) ok = hipMemcpyAsync(verts_dev, verts_host, (size_t)12 * (size_t)nv, hipMemcpyHostToDevice, cs) ==
+                 hipSuccess;
+    ok = ok && hipEventRecord(ev[0], cs) == hipSuccess;
+    for (int64_t i = 0; ok && i < nslices; ++i) {
+        const int64_t t0 = i * per, n = per ? (nt - t0 < per ? nt - t0 : per) : 0;
+        if (n) ok = hipMemcpyAsync(tets_dev + 4 * t0, tets_host + 4 * t0, (size_t)16 * (size_t)n,
+                                   hipMemcpyHostToDevice, cs) == hipSuccess;
+        ok = ok && hipEventRecord(ev[(size_t)i + 1], cs) == hipSuccess;
+    }
+    ok = ok && hipStreamWaitEvent(s, ev[0], 0) == hipSuccess;
+    for (int64_t i = 0; ok && i < nslices; ++i) {
+        const int64_t t0 = i * per, n = per ? (nt - t0 < per ? nt - t0 : per) : 0;
+        ok = hipStreamWaitEvent(s, ev[(size_t)i + 1], 0) == hipSuccess;
+        if (!ok) break;
+        st = voxelize_one(verts_dev, TV_VERTS_F32, nv, tets_dev + 4 * t0, n, dims, &bbox, grid, ws, ws_bytes,
+                          s, flags | (i ? TV_ACCUMULATE : 0u));
+        if (st) break;
+    }
+    for (auto &e : ev) hipEventDestroy(e);  // released once their work completes
+    if (st) return st;
+    if (!ok) return fail(TV_ERR_HIP, "pipelined copy or wait failed");
+    return check_hip("pipelined voxelize");
 }
 
 tv_status tv_snap(const float *verts, int64_t nv, tv_bbox bbox, int32_t *q_out, void *stream) {

@@ -791,8 +791,13 @@ __global__ void __launch_bounds__(kTileThreads)
             const int32_t cl = x >> p.lw;
             const int64_t i = ti0 + (cl >> p.ly), j = tj0 + (cl & ((1 << p.ly) - 1));
             const int64_t gw = (i * g.n[1] + j) * g.words + zbase + (x & (tw - 1));
-            if (!shared_tile) grid[gw] = wv;
-            else if (wv) __hip_atomic_fetch_or(grid + gw, wv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (shared_tile) {
+                if (wv) __hip_atomic_fetch_or(grid + gw, wv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } else if (!T.accumulate) {
+                grid[gw] = wv;
+            } else if (wv) {
+                grid[gw] |= wv;  // this chunk owns the tile within the call
+            }
         }
         __syncthreads();
     }
