@@ -417,6 +417,7 @@ __device__ __forceinline__ int4 load_int4(gptr<int4> base, int64_t i) {
 constexpr int kTileThreads = 256;
 constexpr int kMaxTileWords = 4096;  // 16 KiB of LDS bitmap
 constexpr int kRowPool = 4096;       // per-batch row entries (16 KiB)
+constexpr uint32_t kNoCullColumns = 3;  // boxes of at most this many columns skip row culling
 
 struct PieceRec {
     Face f[4];
@@ -657,20 +658,31 @@ __global__ void __launch_bounds__(kTileThreads)
             if ((uint32_t)tid < nb && nrows) {
                 PieceRec &R = s_rec[tid];
                 const uint32_t base = s_roff[tid];
-                RowHull hull;
-                make_row_hull(Vt, hull);
                 uint32_t prefix = 0, kept = 0;
-                for (uint32_t rr = 0; rr < nrows; ++rr) {
-                    const double cx = (double)((2 * (lo[0] + (int32_t)rr) + 1) * g.half[0]);
-                    int32_t j0, j1;
-                    row_columns(hull, cx, g, j0, j1);
-                    j0 = max(j0, lo[1]);
-                    j1 = min(j1, hi[1]);
-                    if (j1 >= j0) {
-                        const uint32_t cnt = (uint32_t)(j1 - j0 + 1);
-                        s_row[base + kept] = (uint32_t)(j0 - lo[1]) | (cnt << 8) | (rr << 16) | (prefix << 22);
-                        ++kept;
-                        prefix += cnt;
+                const uint32_t bw = (uint32_t)(hi[1] - lo[1] + 1);
+                if (nrows * bw <= kNoCullColumns) {
+                    // a box this small loses too little to culling to pay for it
+                    for (uint32_t rr = 0; rr < nrows; ++rr) {
+                        s_row[base + rr] = (bw << 8) | (rr << 16) | (prefix << 22);
+                        prefix += bw;
+                    }
+                    kept = nrows;
+                } else {
+                    RowHull hull;
+                    make_row_hull(Vt, hull);
+                    for (uint32_t rr = 0; rr < nrows; ++rr) {
+                        const double cx = (double)((2 * (lo[0] + (int32_t)rr) + 1) * g.half[0]);
+                        int32_t j0, j1;
+                        row_columns(hull, cx, g, j0, j1);
+                        j0 = max(j0, lo[1]);
+                        j1 = min(j1, hi[1]);
+                        if (j1 >= j0) {
+                            const uint32_t cnt = (uint32_t)(j1 - j0 + 1);
+                            s_row[base + kept] =
+                                (uint32_t)(j0 - lo[1]) | (cnt << 8) | (rr << 16) | (prefix << 22);
+                            ++kept;
+                            prefix += cnt;
+                        }
                     }
                 }
                 R.ni = (int16_t)kept;

@@ -97,3 +97,33 @@ def test_bad_mesh_is_isolated(oracle_mod):
             want = oracle_mod.voxelize_q(q, m.tets[keep], m.dims)
         assert np.array_equal(to_numpy_words(grids[i]), want), f"mesh {i}"
     assert b.status(len(ms)) == tv.TV_ERR_INVALID_ARG
+
+
+def test_whole_grid_meshes_check_their_tets(oracle_mod):
+    """Meshes whose grid is a single tile (32^3 in a batch), one of them with
+    many chunks: a bad index flags its mesh, a vertex that fails the snap
+    drops the tets using it, and every other mesh is untouched."""
+    import torch
+
+    import paper_2106_01326_amd as tv
+
+    ms = [synth.make_mesh(8, 0.2, 32, "sphere", 0, 7100 + i) for i in range(3)]
+    ms.append(synth.make_mesh(12, 0.3, 64, "ellipsoids", 2, 7103))  # binned, 4 tiles
+    ms.append(synth.make_mesh(40, 0.3, 32, "all", 0, 7104))  # one tile, many chunks
+    bad_tets = np.concatenate([ms[0].tets, np.array([[0, 1, 2, ms[0].nv + 7], [-3, 1, 2, 3]], np.int32)])
+    nanv = ms[1].verts.copy()
+    nanv[5, 2] = np.nan
+    items = [to_item(m) for m in ms]
+    items[0] = (items[0][0], torch.from_numpy(bad_tets).cuda(), ms[0].dims, ms[0].bbox, False)
+    items[1] = (torch.from_numpy(nanv).cuda(), items[1][1], ms[1].dims, ms[1].bbox, False)
+    b = tv.Batch(items)
+    grids = b.run()
+    assert [b.status(i) for i in range(len(ms))] == [tv.TV_ERR_INDEX, tv.TV_ERR_RANGE, tv.TV_OK, tv.TV_OK,
+                                                    tv.TV_OK]
+    for i, m in enumerate(ms):
+        want = oracle_mod.voxelize_mesh(m)
+        if i == 1:
+            keep = ~np.any(m.tets == 5, axis=1)
+            q = oracle_mod.snap(np.where(np.isnan(nanv), 0, nanv), *m.bbox)
+            want = oracle_mod.voxelize_q(q, m.tets[keep], m.dims)
+        assert np.array_equal(to_numpy_words(grids[i]), want), f"mesh {i}"
