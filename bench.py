@@ -83,12 +83,16 @@ def candidate_work(q, tets, dims):
     return int(nonempty.sum()), int(cols.sum()), int(cand.sum())
 
 
+# the sources that build and launch the tile kernel (its counters go stale
+# when one of these changes)
+TILE_KERNEL_SOURCES = ("tv_kernels.hip", "tv_kernels.h", "tv_common.h", "tv_workspace.h", "tv_api.hip")
+
+
 def kernel_source_sha():
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2106_01326_amd", "csrc")
-    for fn in sorted(os.listdir(csrc)):
-        if fn.endswith((".hip", ".h")):
-            h.update(open(os.path.join(csrc, fn), "rb").read())
+    for fn in TILE_KERNEL_SOURCES:
+        h.update(open(os.path.join(csrc, fn), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -132,6 +136,25 @@ def cpu_baseline(m, gpu_words_fn, target_s=12.0):
     return {"value": n / dt, "unit": "tets/s", "cores": cores, "kind": "oracle",
             "sample": f"first {n} of {m.nt} tets (snap + voxelize, {dt:.1f} s wall)",
             "seconds": dt, "gpu_bit_exact_on_sample": exact}
+
+
+def tile_roofline(torch, tv, items, meshes, vox_ms):
+    """The tile kernel against the VALU peak for a call over `meshes`
+    (device vertex tensors in items[i][0]): algorithmic ops from the lattice
+    vertices (snapped on the device), divided by the measured voxelize-stage
+    time per call."""
+    ne = cols = 0
+    for (v, _, dims, bbox, _), m in zip(items, meshes):
+        q = tv.snap(v, bbox).cpu().numpy()
+        a, b, _ = candidate_work(q, m.tets, dims)
+        ne += a
+        cols += b
+    ops = SETUP_OPS_PER_TET * ne + OPS_PER_COLUMN * cols
+    achieved = ops / (vox_ms * 1e-3) / 1e12 if vox_ms > 0 else None
+    return {"bound": "alu", "kernel": "k_tile_voxelize", "achieved": achieved, "peak": VALU_PEAK_TOPS,
+            "unit": "TOP/s", "frac": achieved / VALU_PEAK_TOPS if achieved else None, "traffic": None,
+            "kernel_ms": vox_ms, "ops_per_launch": ops,
+            "units": {"tets_nonempty": ne, "candidate_columns": cols}}
 
 
 def bench_batch(args, torch, tv):
@@ -201,6 +224,7 @@ def bench_batch(args, torch, tv):
                              "host_wall_ms_per_pass": wall_loop},
            "batched_over_per_mesh": ms_loop / ms_batch, "bit_identical_to_per_mesh": bool(same),
            "stage_ms": {k: v_ / max(calls, 1) for k, v_ in stages.items()}}
+    out["roofline"] = tile_roofline(torch, tv, items, meshes, stages.get("voxelize", 0.0) / max(calls, 1))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_batch(meshes, batch, args.cpu_seconds)
     else:
@@ -291,7 +315,11 @@ def bench_serving(args, torch, tv):
            "data": "synthetic (seeded jittered Kuhn meshes)",
            "config": {"workload": "Poisson request stream", "mix": "90% batch distribution, 10% medium shape",
                       "pool": "512 + 32 meshes", "inputs": "pinned host memory", "streams": 2},
-           "serving": res, "server_stats": {k: int(v) for k, v in st.items()}, "cpu_baseline": None}
+           "serving": res, "server_stats": {k: int(v) for k, v in st.items()},
+           "roofline": None,
+           "roofline_note": "bound by the host-to-device copies of the requests' inputs over PCIe, not by a "
+                            "kernel (the device-resident rates are in the batch and sweep lines)",
+           "cpu_baseline": None}
     print(json.dumps(out), flush=True)
 
 
@@ -509,12 +537,19 @@ def bench_sweep(args, torch, tv):
             for _ in range(2):
                 fn()
             torch.cuda.synchronize()
+            if name == "device":
+                tv.profile_read()
+                tv.profile_enable(True)
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(stream)
             for _ in range(steps):
                 fn()
             e1.record(stream)
             torch.cuda.synchronize()
+            if name == "device":
+                tv.profile_enable(False)
+                stages, calls = tv.profile_read()
+                vox_ms = stages.get("voxelize", 0.0) / max(calls, 1)
             res[name] = e0.elapsed_time(e1) / steps
         in_bytes = m.verts.nbytes + m.tets.nbytes
         row = {"n": n, "tets": m.nt, "verts": m.nv, "device_ms": res["device"], "pcie_ms": res["pcie"],
@@ -525,6 +560,7 @@ def bench_sweep(args, torch, tv):
             want = oracle.voxelize_q(oracle.snap(m.verts, *m.bbox), m.tets, m.dims, threads=cores)
             row["cpu_oracle_ms"] = (time.perf_counter() - t0) * 1e3
             row["bit_exact"] = bool(np.array_equal(grid_h.numpy().view(np.uint32), want))
+        row["roofline"] = tile_roofline(torch, tv, [(v_d, t_d, m.dims, m.bbox, False)], [m], vox_ms)
         log(f"sweep {row}")
         rows.append(row)
         del v_d, t_d, grid, ws, ws_pipe
@@ -536,7 +572,7 @@ def bench_sweep(args, torch, tv):
            "data": "synthetic (seeded jittered Kuhn meshes, all tets kept)",
            "config": {"workload": "Table 1 sweep: 1e5 / 1e6 / 1e7 tets at 256^3", "grid": [256, 256, 256],
                       "cubes_per_axis": list(SWEEP_N)},
-           "sweep": rows,
+           "sweep": rows, "roofline": big["roofline"],
            "paper_table1": "RTX 3080 + i7-10700 (other hardware, context only): 1e5 tets 1.665 s CPU+GPU vs "
                            "0.503 s CPU; 1e6 2.776 s vs 2.947 s; 1e7 9.77 s vs 98.931 s",
            "cpu_baseline": None if args.no_cpu_baseline else {

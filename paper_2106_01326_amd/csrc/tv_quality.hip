@@ -194,13 +194,31 @@ __global__ void __launch_bounds__(kThreads)
     }
 }
 
+// Set bits of the grid: 16-byte loads (grids from the library are 256-byte
+// aligned) with a word-wise tail.
 __global__ void __launch_bounds__(kThreads)
     k_popcount(const uint32_t *__restrict__ grid, int64_t n, unsigned long long *__restrict__ acc) {
     unsigned long long s = 0;
-    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
-        s += (unsigned long long)__popc(grid[i]);
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    const int64_t t0 = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    const bool vec = (reinterpret_cast<uintptr_t>(grid) & 15u) == 0;
+    const int64_t n4 = vec ? n / 4 : 0;
+    const uint4 *g4 = reinterpret_cast<const uint4 *>(grid);
+    for (int64_t i = t0; i < n4; i += stride) {
+        const uint4 w = g4[i];
+        s += (unsigned long long)(__popc(w.x) + __popc(w.y) + __popc(w.z) + __popc(w.w));
+    }
+    for (int64_t i = 4 * n4 + t0; i < n; i += stride) s += (unsigned long long)__popc(grid[i]);
+    // one atomic per block (the counter is a single contended address)
+    __shared__ unsigned long long s_w[kThreads / 64];
     s = wave_sum(s);
-    if ((threadIdx.x & 63) == 0 && s) atomicAdd(acc + kOccupied, s);
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < kThreads / 64; ++w) t += s_w[w];
+        if (t) atomicAdd(acc + kOccupied, t);
+    }
 }
 
 bool pow2_dim(int32_t n) { return n >= 1 && n <= 32768 && (n & (n - 1)) == 0; }
@@ -263,7 +281,8 @@ tv_status tv_mesh_quality(const void *verts, uint32_t vert_format, int64_t nv, c
             q, nv, reinterpret_cast<const int4 *>(tets), nt, g, scale[0], scale[1], scale[2],
             (flags & TV_TIE_STRICT) ? 1 : 0, acc);
     const int64_t nwords = (int64_t)dims.nx * dims.ny * g.words;
-    k_popcount<<<1024, kThreads, 0, s>>>(grid, nwords, acc);
+    const int64_t want = (nwords / 4 + kThreads - 1) / kThreads;
+    k_popcount<<<(unsigned)(want < 1 ? 1 : (want > 2048 ? 2048 : want)), kThreads, 0, s>>>(grid, nwords, acc);
     unsigned long long h[kSlots];
     if (hipMemcpyAsync(h, acc, sizeof h, hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
