@@ -260,6 +260,17 @@ def test_tets_straddling_tile_corners(oracle_mod):
     assert_same(got, want, "tile-corner tets")
 
 
+@pytest.mark.parametrize("strict", [False, True])
+def test_tets_smaller_than_voxels(oracle_mod, strict):
+    """More tets than voxels (the regime where small pieces are finished as
+    soon as their faces are built, next to larger ones in the same tiles)."""
+    m = synth.make_mesh(40, 0.4, 64, "all", 0, 1006)
+    banner(f"{m.nt} tets in a 64^3 grid, strict={strict}")
+    got, st = gpu_voxelize_mesh(m, strict=strict)
+    assert st == 0
+    assert_same(got, oracle_words(oracle_mod, m, strict=strict), "small tets")
+
+
 def test_repeatable_bit_identical():
     m = synth.make_mesh(16, 0.4, 64, "ellipsoids", 4, 707)
     ref, _ = gpu_voxelize_mesh(m)
@@ -311,3 +322,33 @@ def test_large_workload_sampled_windows(oracle_mod, large):
     # global properties: padding-free layout, set count within a sane range
     nset = int(np.unpackbits(got.view(np.uint8)).sum())
     assert 0.05 * n ** 3 < nset < 0.95 * n ** 3
+
+
+def test_full_size_cube_partition():
+    """At the large configuration's full size (128^3 Kuhn cells, 12.6M tets,
+    jitter 0.45, 1024^3 grid) with every tet kept: the grid is all ones, and
+    two random halves of the tets give disjoint grids whose union is all ones
+    -- each voxel center covered exactly once by a conforming mesh under the
+    half-open rule.  A property that holds at any size, checked in the launch
+    configuration bench.py times."""
+    import torch
+
+    import paper_2106_01326_amd as tv
+
+    m = synth.make_mesh(128, 0.45, 1024, "all", 0, 2)
+    banner(f"full-size cube partition: {m.nt} tets")
+    v = torch.from_numpy(m.verts).cuda()
+    rng = np.random.default_rng(2024)
+    side = rng.random(m.nt) < 0.5
+    grids = []
+    for tets in (m.tets, m.tets[side], m.tets[~side]):
+        t = torch.from_numpy(np.ascontiguousarray(tets)).cuda()
+        g, ws = tv.voxelize(v, t, m.dims, m.bbox)
+        assert tv.fetch_status(ws) == tv.TV_OK
+        grids.append(g)
+        del t, ws
+    full, a, b = grids
+    ones = torch.full_like(full, -1)
+    assert torch.equal(full, ones)
+    assert not torch.any(a & b)
+    assert torch.equal(a | b, ones)
