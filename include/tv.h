@@ -267,9 +267,11 @@ tv_status tv_server_destroy(tv_server *s);
  * be pinned for the copies to run asynchronously.  `ws` needs
  * tv_workspace_bytes(nv, ceil(nt / chunks), dims, flags) bytes.  chunks is
  * clamped to [1, 64]; every slice repeats the launch sequence (and the snap
- * of all vertices), so slices of about a million tets or more pay off.
- * Returns after enqueueing; `stream` orders after all the copies.  flags:
- * TV_TIE_STRICT, TV_PATH_PER_TET.
+ * of all vertices), so slices of about a million tets or more pay off.  With
+ * one slice the copies simply run on `stream`.  The library keeps a small pool
+ * of HIP events per calling thread and device for the slices.  Returns after
+ * enqueueing; `stream` orders after all the copies.  flags: TV_TIE_STRICT,
+ * TV_PATH_PER_TET.
  */
 tv_status tv_voxelize_pipelined(const float *verts_host, int64_t nv, const int32_t *tets_host,
                                 int64_t nt, tv_dims dims, tv_bbox bbox, float *verts_dev,

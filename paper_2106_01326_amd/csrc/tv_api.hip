@@ -354,13 +354,30 @@ tv_status tv_voxelize_pipelined(const float *verts_host, int64_t nv, const int32
     if (st) return st;
     if ((st = check_ws(ws, ws_bytes, tv_workspace_bytes(nv, per, dims, flags), flags))) return st;
     const int64_t nslices = per ? (nt + per - 1) / per : 1;
-    std::vector<hipEvent_t> ev((size_t)nslices + 1, nullptr);
-    for (auto &e : ev)
-        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
-            for (auto &x : ev)
-                if (x) hipEventDestroy(x);
+    if (nslices == 1) {
+        // nothing to overlap: copy and voxelize in order on one stream
+        bool ok = true;
+        if (nv) ok = hipMemcpyAsync(verts_dev, verts_host, (size_t)12 * (size_t)nv, hipMemcpyHostToDevice, s) ==
+                     hipSuccess;
+        if (nt) ok = ok && hipMemcpyAsync(tets_dev, tets_host, (size_t)16 * (size_t)nt, hipMemcpyHostToDevice,
+                                          s) == hipSuccess;
+        if (!ok) return fail(TV_ERR_HIP, "pipelined copy failed");
+        return voxelize_one(verts_dev, TV_VERTS_F32, nv, tets_dev, nt, dims, &bbox, grid, ws, ws_bytes, s,
+                            flags);
+    }
+    // events come from a per-thread, per-device pool (recording an event again
+    // does not disturb waits already enqueued on its earlier record)
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(TV_ERR_HIP, "no current device");
+    thread_local std::vector<std::vector<hipEvent_t>> pool;
+    if ((size_t)dev >= pool.size()) pool.resize((size_t)dev + 1);
+    std::vector<hipEvent_t> &ev = pool[(size_t)dev];
+    while (ev.size() < (size_t)nslices + 1) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
             return fail(TV_ERR_HIP, "event creation failed");
-        }
+        ev.push_back(e);
+    }
     bool ok = true;
     if (nv) ok = hipMemcpyAsync(verts_dev, verts_host, (size_t)12 * (size_t)nv, hipMemcpyHostToDevice, cs) ==
                  hipSuccess;
@@ -380,7 +397,6 @@ tv_status tv_voxelize_pipelined(const float *verts_host, int64_t nv, const int32
                           s, flags | (i ? TV_ACCUMULATE : 0u));
         if (st) break;
     }
-    for (auto &e : ev) hipEventDestroy(e);  // released once their work completes
     if (st) return st;
     if (!ok) return fail(TV_ERR_HIP, "pipelined copy or wait failed");
     return check_hip("pipelined voxelize");
