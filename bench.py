@@ -493,7 +493,6 @@ def bench_sweep(args, torch, tv):
     cells, all kept) voxelized into 256^3, timed three ways: inputs already
     in HBM; inputs in pinned host memory copied in, grid copied back
     (PCIe-inclusive, one stream); and the CPU oracle on the host cores."""
-    import oracle
     from paper_2106_01326_amd import synth
 
     dev = torch.device("cuda:0")
@@ -556,6 +555,8 @@ def bench_sweep(args, torch, tv):
                "pcie_pipelined_ms": res["pcie_pipelined"], "pipelined_slices": slices,
                "h2d_bytes": in_bytes, "d2h_bytes": grid.numel() * 4}
         if not args.no_cpu_baseline:
+            import oracle
+
             t0 = time.perf_counter()
             want = oracle.voxelize_q(oracle.snap(m.verts, *m.bbox), m.tets, m.dims, threads=cores)
             row["cpu_oracle_ms"] = (time.perf_counter() - t0) * 1e3
