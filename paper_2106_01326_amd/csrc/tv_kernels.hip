@@ -213,6 +213,7 @@ __device__ __forceinline__ int32_t tet_pieces(const MeshDesc &d, const int4 *__r
 // key and the tile range's shape), so the scatter pass reads 8 bytes per tet
 // instead of gathering and boxing the tet again.
 constexpr int kBinThreads = 256;
+constexpr int kBinTets = 2;  // tets per thread
 constexpr int kHashSlots = 512;
 constexpr int kHashProbes = 32;
 constexpr int kPieceCapMax = 8;
@@ -244,49 +245,63 @@ template <bool kScatter>
 __global__ void __launch_bounds__(kBinThreads) k_bin(MeshTable T, BinBuffers b) {
     __shared__ uint32_t s_key[kHashSlots];
     __shared__ uint32_t s_cnt[kHashSlots];  // count, then (pass 2) global slot base
-    __shared__ uint32_t s_ref[kBinThreads * kPieceCapMax];  // slot << 16 | rank, or kNoSlot
+    __shared__ uint32_t s_ref[kBinTets * kBinThreads * kPieceCapMax];  // slot << 16 | rank, or kNoSlot
     __shared__ int32_t s_bracket[2];
     const int tid = threadIdx.x;
     for (int i = tid; i < kHashSlots; i += kBinThreads) {
         s_key[i] = kEmptyKey;
         s_cnt[i] = 0u;
     }
-    __syncthreads();
-    const int64_t first = (int64_t)blockIdx.x * kBinThreads;
-    const int64_t last = min(first + (int64_t)kBinThreads, T.nt_total) - 1;
-    const int64_t t = first + tid;
-    const int32_t m = find_mesh_block(T, T.tet_pre, first, last, min(t, last), s_bracket);
-    int32_t np = 0;
-    if (t < T.nt_total) {
-        const MeshDesc &d = mesh_desc(T, m);
-        uint32_t key0 = 0;
-        int32_t nx = 1, ny = 1, nz = 1;
-        if (!kScatter) {
-            TileRange r = {0, -1, 0, -1, 0, -1};
-            np = tet_pieces(d, b.q4, t - d.tet_base, b.status, r);
-            if (np > T.piece_cap) {
-                b.big[atomicAdd(&b.meta[kMetaBig], 1u)] = (uint32_t)t;
-                np = 0;
-            }
-            key0 = (uint32_t)d.tile_base + tile_id(r.x0, r.y0, r.z0, d.p);
-            b.trec[t] = encode_trec(key0, r, np);
-            ny = r.y1 - r.y0 + 1;
-            nz = r.z1 - r.z0 + 1;
-        } else {
-            const uint2 rec = b.trec[t];
-            if (rec.y) {
-                key0 = rec.x;
-                nx = (int32_t)((rec.y >> 1) & 7u) + 1;
-                ny = (int32_t)((rec.y >> 4) & 7u) + 1;
-                nz = (int32_t)((rec.y >> 7) & 7u) + 1;
-                np = nx * ny * nz;
+    // each thread takes kBinTets tets, kBinThreads apart (coalesced): first
+    // all their tile ranges (independent gathers in flight together), then
+    // their pieces into the table
+    const int64_t first = (int64_t)blockIdx.x * (kBinThreads * kBinTets);
+    const int64_t last = min(first + (int64_t)(kBinThreads * kBinTets), T.nt_total) - 1;
+    int32_t np[kBinTets], nys[kBinTets], nzs[kBinTets];
+    uint32_t key0s[kBinTets], sys[kBinTets], sxs[kBinTets];
+#pragma unroll
+    for (int u = 0; u < kBinTets; ++u) {
+        const int64_t t = first + u * kBinThreads + tid;
+        const int32_t m = find_mesh_block(T, T.tet_pre, first, last, min(t, last), s_bracket);
+        np[u] = 0;
+        nys[u] = nzs[u] = 1;
+        key0s[u] = sys[u] = sxs[u] = 0;
+        if (t < T.nt_total) {
+            const MeshDesc &d = mesh_desc(T, m);
+            sys[u] = (uint32_t)d.p.ntz;
+            sxs[u] = (uint32_t)d.p.nty * sys[u];
+            if (!kScatter) {
+                TileRange r = {0, -1, 0, -1, 0, -1};
+                int32_t n = tet_pieces(d, b.q4, t - d.tet_base, b.status, r);
+                if (n > T.piece_cap) {
+                    b.big[atomicAdd(&b.meta[kMetaBig], 1u)] = (uint32_t)t;
+                    n = 0;
+                }
+                key0s[u] = (uint32_t)d.tile_base + tile_id(r.x0, r.y0, r.z0, d.p);
+                b.trec[t] = encode_trec(key0s[u], r, n);
+                np[u] = n;
+                nys[u] = r.y1 - r.y0 + 1;
+                nzs[u] = r.z1 - r.z0 + 1;
+            } else {
+                const uint2 rec = b.trec[t];
+                if (rec.y) {
+                    key0s[u] = rec.x;
+                    const int32_t nx = (int32_t)((rec.y >> 1) & 7u) + 1;
+                    nys[u] = (int32_t)((rec.y >> 4) & 7u) + 1;
+                    nzs[u] = (int32_t)((rec.y >> 7) & 7u) + 1;
+                    np[u] = nx * nys[u] * nzs[u];
+                }
             }
         }
-        const uint32_t sy = (uint32_t)d.p.ntz, sx = (uint32_t)d.p.nty * sy;
-        for (int32_t k = 0; k < np; ++k) {
-            const int32_t dz = k % nz, rest = k / nz;
-            const int32_t dy = rest % ny, dx = rest / ny;
-            const uint32_t key = key0 + (uint32_t)dx * sx + (uint32_t)dy * sy + (uint32_t)dz;
+    }
+    __syncthreads();  // the table is clear
+#pragma unroll
+    for (int u = 0; u < kBinTets; ++u) {
+        const int64_t t = first + u * kBinThreads + tid;
+        for (int32_t k = 0; k < np[u]; ++k) {
+            const int32_t dz = k % nzs[u], rest = k / nzs[u];
+            const int32_t dy = rest % nys[u], dx = rest / nys[u];
+            const uint32_t key = key0s[u] + (uint32_t)dx * sxs[u] + (uint32_t)dy * sys[u] + (uint32_t)dz;
             const uint32_t h = hash_insert(s_key, key);
             uint32_t ref = kNoSlot;
             if (h != kNoSlot) {
@@ -296,7 +311,7 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(MeshTable T, BinBuffers b) 
             } else {
                 atomicAdd(b.tile_count + key, 1u);
             }
-            s_ref[tid * kPieceCapMax + k] = ref;
+            s_ref[(u * kBinThreads + tid) * kPieceCapMax + k] = ref;
         }
     }
     __syncthreads();
@@ -308,9 +323,13 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(MeshTable T, BinBuffers b) 
     }
     if (!kScatter) return;
     __syncthreads();
-    for (int32_t k = 0; k < np; ++k) {
-        const uint32_t ref = s_ref[tid * kPieceCapMax + k];
-        if (ref != kNoSlot) b.pieces[s_cnt[ref >> 16] + (ref & 0xffffu)] = (uint32_t)t;
+#pragma unroll
+    for (int u = 0; u < kBinTets; ++u) {
+        const int64_t t = first + u * kBinThreads + tid;
+        for (int32_t k = 0; k < np[u]; ++k) {
+            const uint32_t ref = s_ref[(u * kBinThreads + tid) * kPieceCapMax + k];
+            if (ref != kNoSlot) b.pieces[s_cnt[ref >> 16] + (ref & 0xffffu)] = (uint32_t)t;
+        }
     }
 }
 
@@ -318,47 +337,55 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(MeshTable T, BinBuffers b) 
 // threads, any tile count): tile_off[t] is the first piece slot of tile t;
 // chunk_off[t] the first chunk; meta[kMetaChunks] the chunk total.
 __global__ void __launch_bounds__(1024) k_scan_tiles(MeshTable T, BinBuffers b) {
-    __shared__ uint32_t s_cnt[1024], s_chk[1024];
+    __shared__ uint32_t s_wc[16], s_wk[16];  // per-wave totals, then their exclusive prefix
     __shared__ uint32_t s_base_cnt, s_base_chk;
     const uint32_t nt = (uint32_t)T.ntiles_total;
     const uint32_t chunk = (uint32_t)T.chunk;
-    const int tid = threadIdx.x;
-    if (tid == 0) {
-        s_base_cnt = 0;
-        s_base_chk = 0;
-    }
-    __syncthreads();
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    uint32_t base_cnt = 0, base_chk = 0;  // totals of the tiles before this round
     for (uint32_t base = 0; base < nt; base += 1024) {
         const uint32_t i = base + tid;
         const uint32_t c = i < nt ? b.tile_count[i] : 0u;
         const uint32_t k = i < nt ? (c == 0 ? 1u : (c + chunk - 1) / chunk) : 0u;
-        s_cnt[tid] = c;
-        s_chk[tid] = k;
-        __syncthreads();
-        // Hillis-Steele inclusive scan
-        for (int off = 1; off < 1024; off <<= 1) {
-            const uint32_t a = tid >= off ? s_cnt[tid - off] : 0u;
-            const uint32_t e = tid >= off ? s_chk[tid - off] : 0u;
-            __syncthreads();
-            s_cnt[tid] += a;
-            s_chk[tid] += e;
-            __syncthreads();
+        // inclusive scans within the wave
+        uint32_t ic = c, ik = k;
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t oc = __shfl_up(ic, off), ok = __shfl_up(ik, off);
+            if (lane >= off) {
+                ic += oc;
+                ik += ok;
+            }
         }
+        if (lane == 63) {
+            s_wc[wv] = ic;
+            s_wk[wv] = ik;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t ac = base_cnt, ak = base_chk;
+            for (int w = 0; w < 16; ++w) {
+                const uint32_t tc = s_wc[w], tk = s_wk[w];
+                s_wc[w] = ac;
+                s_wk[w] = ak;
+                ac += tc;
+                ak += tk;
+            }
+            s_base_cnt = ac;
+            s_base_chk = ak;
+        }
+        __syncthreads();
         if (i < nt) {
-            b.tile_off[i] = s_base_cnt + s_cnt[tid] - c;
-            b.chunk_off[i] = s_base_chk + s_chk[tid] - k;
+            b.tile_off[i] = s_wc[wv] + ic - c;
+            b.chunk_off[i] = s_wk[wv] + ik - k;
         }
-        __syncthreads();
-        if (tid == 1023) {
-            s_base_cnt += s_cnt[1023];
-            s_base_chk += s_chk[1023];
-        }
-        __syncthreads();
+        base_cnt = s_base_cnt;
+        base_chk = s_base_chk;
+        __syncthreads();  // s_wc / s_wk are rewritten next round
     }
     if (tid == 0) {
-        b.tile_off[nt] = s_base_cnt;
-        b.chunk_off[nt] = s_base_chk;
-        b.meta[kMetaChunks] = s_base_chk;
+        b.tile_off[nt] = base_cnt;
+        b.chunk_off[nt] = base_chk;
+        b.meta[kMetaChunks] = base_chk;
     }
 }
 
@@ -919,7 +946,7 @@ void launch_set_word(uint32_t *p, uint32_t value, hipStream_t s) {
 
 void launch_bin_count(const MeshTable &T, const BinBuffers &b, hipStream_t s) {
     if (T.nt_total > 0)
-        k_bin<false><<<blocks_for(T.nt_total, kBinThreads), kBinThreads, 0, s>>>(T, b);
+        k_bin<false><<<blocks_for(T.nt_total, kBinThreads * kBinTets), kBinThreads, 0, s>>>(T, b);
 }
 
 void launch_scan_tiles(const MeshTable &T, const BinBuffers &b, hipStream_t s) {
@@ -928,7 +955,7 @@ void launch_scan_tiles(const MeshTable &T, const BinBuffers &b, hipStream_t s) {
 
 void launch_bin_scatter(const MeshTable &T, const BinBuffers &b, hipStream_t s) {
     if (T.nt_total > 0)
-        k_bin<true><<<blocks_for(T.nt_total, kBinThreads), kBinThreads, 0, s>>>(T, b);
+        k_bin<true><<<blocks_for(T.nt_total, kBinThreads * kBinTets), kBinThreads, 0, s>>>(T, b);
 }
 
 void launch_zero_shared_tiles(const MeshTable &T, const BinBuffers &b, hipStream_t s) {
