@@ -38,7 +38,11 @@
  * returns, aligned to 256 bytes.  Calls are asynchronous on `stream` (a
  * hipStream_t; NULL is the default stream) and return after enqueueing.
  * Calls on different streams with different workspaces may run concurrently;
- * two calls sharing a workspace must be ordered on one stream.
+ * two calls sharing a workspace must be ordered on one stream.  A single-mesh
+ * call (tv_voxelize, tv_voxelize_q) and the grid consumers enqueue kernels
+ * only, so they can be captured in a HIP graph and replayed (same pointers
+ * and sizes); tv_voxelize_batch copies its mesh table from host memory and
+ * must not be captured.
  *
  * Errors: argument errors that the host can see (null pointers, sizes, dims,
  * bbox, workspace size) return synchronously and enqueue nothing.  Data errors
