@@ -39,10 +39,10 @@
  * hipStream_t; NULL is the default stream) and return after enqueueing.
  * Calls on different streams with different workspaces may run concurrently;
  * two calls sharing a workspace must be ordered on one stream.  A single-mesh
- * call (tv_voxelize, tv_voxelize_q) and the grid consumers enqueue kernels
- * only, so they can be captured in a HIP graph and replayed (same pointers
- * and sizes); tv_voxelize_batch copies its mesh table from host memory and
- * must not be captured.
+ * call (tv_voxelize, tv_voxelize_q), tv_batch_run and the grid consumers
+ * enqueue kernels only, so they can be captured in a HIP graph and replayed
+ * (same pointers and sizes); tv_voxelize_batch and tv_batch_prepare copy the
+ * mesh table from host memory and must not be captured.
  *
  * Errors: argument errors that the host can see (null pointers, sizes, dims,
  * bbox, workspace size) return synchronously and enqueue nothing.  Data errors
@@ -151,6 +151,41 @@ typedef struct {
 size_t tv_batch_workspace_bytes(const tv_mesh *meshes, int32_t n, uint32_t flags);
 tv_status tv_voxelize_batch(const tv_mesh *meshes, int32_t n, void *ws, size_t ws_bytes,
                             void *stream, uint32_t flags);
+
+/*
+ * The batch call in two steps, for callers that repeat one batch (a HIP
+ * graph replay, a loop over fixed device buffers).  The operation is the
+ * one above (Section 3: every tet of every mesh, voxel centers tested
+ * against it); only the descriptor upload is split off.
+ *
+ * tv_batch_prepare checks the meshes as tv_voxelize_batch does, copies their
+ * descriptor table into `ws` (asynchronously on `stream`, from pageable
+ * host memory, so `meshes` may be reused when it returns) and fills *plan, a
+ * small host struct owned by the caller.  It enqueues no kernel.
+ * TV_PATH_PER_TET is rejected (TV_ERR_INVALID_ARG).
+ *
+ * tv_batch_run enqueues the batch's kernels on `stream` and nothing else: no
+ * host copies, memsets or allocations, so a run can be captured in a HIP
+ * graph and replayed (with stage profiling off while capturing).  Each run
+ * voxelizes the current contents of the meshes' vertex and tet buffers into
+ * their grids, bit for bit as tv_voxelize_batch, with the flags given to
+ * tv_batch_prepare; status words as for tv_voxelize_batch.  `ws` must be
+ * the workspace the plan was prepared in (else TV_ERR_INVALID_ARG), still
+ * holding the table: any other call that uses `ws` in between overwrites
+ * it, and the batch must then be prepared again.  A plan not filled by
+ * tv_batch_prepare, or edited, is rejected with TV_ERR_INVALID_ARG.  Runs
+ * sharing one workspace must be ordered on one stream.
+ */
+typedef struct {
+    int64_t meshes, nv, nt, ntiles; /* totals of the prepared batch */
+    uint64_t ws;                    /* address of the workspace holding the table */
+    uint32_t flags;                 /* flags given to tv_batch_prepare */
+    uint32_t check;                 /* consistency tag */
+} tv_batch_plan;
+
+tv_status tv_batch_prepare(const tv_mesh *meshes, int32_t n, void *ws, size_t ws_bytes,
+                           void *stream, uint32_t flags, tv_batch_plan *plan);
+tv_status tv_batch_run(const tv_batch_plan *plan, void *ws, size_t ws_bytes, void *stream);
 
 /*
  * Snap only: fp32 world coordinates verts [nv][3] -> lattice coordinates

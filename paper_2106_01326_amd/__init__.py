@@ -40,7 +40,7 @@ VERTS_F32 = 0
 VERTS_Q32 = 1
 
 EXPORTED = ("tv_grid_words", "tv_workspace_bytes", "tv_voxelize", "tv_voxelize_q", "tv_snap",
-            "tv_batch_workspace_bytes", "tv_voxelize_batch",
+            "tv_batch_workspace_bytes", "tv_voxelize_batch", "tv_batch_prepare", "tv_batch_run",
             "tv_fetch_status", "tv_status_string", "tv_last_error", "tv_profile_enable",
             "tv_profile_read", "tv_profile_stage_name", "tv_server_create", "tv_server_submit",
             "tv_server_poll", "tv_server_wait", "tv_server_result", "tv_server_copy_grid",
@@ -72,6 +72,12 @@ class MeshC(ctypes.Structure):
     _fields_ = [("verts", ctypes.c_void_p), ("vert_format", ctypes.c_uint32), ("nv", ctypes.c_int64),
                 ("tets", ctypes.c_void_p), ("nt", ctypes.c_int64), ("dims", Dims), ("bbox", BBox),
                 ("grid", ctypes.c_void_p)]
+
+
+class BatchPlanC(ctypes.Structure):
+    _fields_ = [("meshes", ctypes.c_int64), ("nv", ctypes.c_int64), ("nt", ctypes.c_int64),
+                ("ntiles", ctypes.c_int64), ("ws", ctypes.c_uint64), ("flags", ctypes.c_uint32),
+                ("check", ctypes.c_uint32)]
 
 
 class HostMeshC(ctypes.Structure):
@@ -150,6 +156,11 @@ def load_library():
     lib.tv_batch_workspace_bytes.restype = ctypes.c_size_t
     lib.tv_voxelize_batch.argtypes = [P, ctypes.c_int32, P, ctypes.c_size_t, P, u32]
     lib.tv_voxelize_batch.restype = st
+    lib.tv_batch_prepare.argtypes = [P, ctypes.c_int32, P, ctypes.c_size_t, P, u32,
+                                     ctypes.POINTER(BatchPlanC)]
+    lib.tv_batch_prepare.restype = st
+    lib.tv_batch_run.argtypes = [ctypes.POINTER(BatchPlanC), P, ctypes.c_size_t, P]
+    lib.tv_batch_run.restype = st
     lib.tv_snap.argtypes = [P, i64, BBox, P, P]
     lib.tv_snap.restype = st
     lib.tv_fetch_status.argtypes = [P, ctypes.c_int32, P]
@@ -536,6 +547,27 @@ class Batch:
         _check(lib.tv_voxelize_batch(ctypes.cast(self.array, ctypes.c_void_p), self.n,
                                      ctypes.c_void_p(self.workspace.data_ptr()), self.workspace.numel(),
                                      _stream_handle(stream), flags))
+        return self.grids
+
+    def prepare(self, strict=False, accumulate=False, stream=None):
+        """Uploads the descriptor table into the workspace (tv_batch_prepare);
+        afterwards ``run_prepared`` enqueues kernels only and may be captured
+        in a HIP graph.  Any other call on this batch's workspace (``run``)
+        overwrites the table, so prepare again after one."""
+        flags = (TIE_STRICT if strict else TIE_HALF_OPEN) | (ACCUMULATE if accumulate else 0)
+        self.plan = BatchPlanC()
+        _check(load_library().tv_batch_prepare(ctypes.cast(self.array, ctypes.c_void_p), self.n,
+                                               ctypes.c_void_p(self.workspace.data_ptr()),
+                                               self.workspace.numel(), _stream_handle(stream), flags,
+                                               ctypes.byref(self.plan)))
+        return self.plan
+
+    def run_prepared(self, stream=None):
+        """One run of the prepared batch (tv_batch_run)."""
+        if getattr(self, "plan", None) is None:
+            raise TVError(TV_ERR_INVALID_ARG, "prepare() the batch first")
+        _check(load_library().tv_batch_run(ctypes.byref(self.plan), ctypes.c_void_p(self.workspace.data_ptr()),
+                                           self.workspace.numel(), _stream_handle(stream)))
         return self.grids
 
     def status(self, i, stream=None):

@@ -118,9 +118,10 @@ tv::MeshDesc make_desc_impl(const void *verts, uint32_t fmt, int64_t nv, const i
     return d;
 }
 
-// Fills the bases of the descriptors and the call totals.
-tv::CallSizes assign_bases_impl(std::vector<tv::MeshDesc> &descs) {
-    tv::CallSizes c = {(int64_t)descs.size(), 0, 0, 0};
+// Fills the bases of the descriptors and the call totals.  `table`: the
+// descriptors go into a device table in the workspace (batch calls).
+tv::CallSizes assign_bases_impl(std::vector<tv::MeshDesc> &descs, bool table) {
+    tv::CallSizes c = {(int64_t)descs.size(), 0, 0, 0, table};
     for (size_t i = 0; i < descs.size(); ++i) {
         tv::MeshDesc &d = descs[i];
         d.mesh = (int32_t)i;
@@ -134,45 +135,63 @@ tv::CallSizes assign_bases_impl(std::vector<tv::MeshDesc> &descs) {
     return c;
 }
 
-// The launch sequence of a call whose descriptors are final.
-tv_status run_impl(std::vector<tv::MeshDesc> &descs, const tv::CallSizes &c, uint8_t *ws, hipStream_t s,
-              uint32_t flags) {
+// Copies the descriptor table and its prefix sums (vertex, tet and tile
+// bases, each with a final total) into the workspace, on `s`.
+tv_status upload_table(const std::vector<tv::MeshDesc> &descs, const tv::CallSizes &c, uint8_t *ws,
+                       hipStream_t s) {
     const tv::WorkspaceLayout L = tv::layout(c);
-    const tv::BinBuffers b = tv::bin_buffers(ws, L);
-    const bool strict = (flags & TV_TIE_STRICT) != 0;
+    std::vector<uint8_t> host(L.descs_bytes);
+    memcpy(host.data(), descs.data(), sizeof(tv::MeshDesc) * descs.size());
+    int64_t *pre = reinterpret_cast<int64_t *>(host.data() + sizeof(tv::MeshDesc) * descs.size());
+    const size_t n = descs.size();
+    for (size_t i = 0; i <= n; ++i) {
+        pre[i] = i < n ? descs[i].vert_base : c.nv;
+        pre[n + 1 + i] = i < n ? descs[i].tet_base : c.nt;
+        pre[2 * (n + 1) + i] = i < n ? descs[i].tile_base : c.ntiles;
+    }
+    if (hipMemcpyAsync(ws + L.descs, host.data(), L.descs_bytes, hipMemcpyHostToDevice, s) !=
+        hipSuccess)
+        return fail(TV_ERR_HIP, "descriptor upload failed");
+    return TV_OK;
+}
+
+// Kernel-side view of a call: the descriptor table in the workspace, or the
+// single descriptor `one` passed by value.
+tv::MeshTable make_table(const tv::CallSizes &c, uint8_t *ws, const tv::MeshDesc *one,
+                         uint32_t flags) {
+    const tv::WorkspaceLayout L = tv::layout(c);
     tv::MeshTable T;
     memset(&T, 0, sizeof T);
     T.n = (int32_t)c.meshes;
     T.chunk = tv::kChunkPieces;
     T.strip = tv::kStripColumns;
     T.piece_cap = tv::kPieceCap;
-    const bool accumulate = (flags & TV_ACCUMULATE) != 0;
-    T.accumulate = accumulate ? 1 : 0;
+    T.accumulate = (flags & TV_ACCUMULATE) ? 1 : 0;
     T.nv_total = c.nv;
     T.nt_total = c.nt;
     T.ntiles_total = c.ntiles;
-    if (c.meshes == 1) {
-        T.one = descs[0];
-    } else {
-        // descriptor table + prefix sums, copied into the workspace
-        std::vector<uint8_t> host(L.descs_bytes);
-        memcpy(host.data(), descs.data(), sizeof(tv::MeshDesc) * descs.size());
-        int64_t *pre = reinterpret_cast<int64_t *>(host.data() + sizeof(tv::MeshDesc) * descs.size());
-        const size_t n = descs.size();
-        for (size_t i = 0; i <= n; ++i) {
-            pre[i] = i < n ? descs[i].vert_base : c.nv;
-            pre[n + 1 + i] = i < n ? descs[i].tet_base : c.nt;
-            pre[2 * (n + 1) + i] = i < n ? descs[i].tile_base : c.ntiles;
-        }
+    if (c.table) {
         uint8_t *dev = ws + L.descs;
-        if (hipMemcpyAsync(dev, host.data(), L.descs_bytes, hipMemcpyHostToDevice, s) != hipSuccess)
-            return fail(TV_ERR_HIP, "descriptor upload failed");
+        const size_t n = (size_t)c.meshes;
         T.descs = reinterpret_cast<const tv::MeshDesc *>(dev);
         const int64_t *dpre = reinterpret_cast<const int64_t *>(dev + sizeof(tv::MeshDesc) * n);
         T.vert_pre = dpre;
         T.tet_pre = dpre + (n + 1);
         T.tile_pre = dpre + 2 * (n + 1);
+    } else {
+        T.one = *one;
     }
+    return T;
+}
+
+// The launch sequence: kernels only (no host copies, memsets or
+// allocations).  `descs` is needed by the per-tet reference path only.
+tv_status enqueue(const tv::MeshTable &T, const tv::CallSizes &c, uint8_t *ws, hipStream_t s,
+                  uint32_t flags, const std::vector<tv::MeshDesc> *descs) {
+    const tv::WorkspaceLayout L = tv::layout(c);
+    const tv::BinBuffers b = tv::bin_buffers(ws, L);
+    const bool strict = (flags & TV_TIE_STRICT) != 0;
+    const bool accumulate = (flags & TV_ACCUMULATE) != 0;
     tv::profile_count_call();
     {
         tv::StageScope sc(tv::kStageClear, s);
@@ -192,8 +211,9 @@ tv_status run_impl(std::vector<tv::MeshDesc> &descs, const tv::CallSizes &c, uin
     tv_status st = check_hip("ingest launch");
     if (st) return st;
     if (flags & TV_PATH_PER_TET) {
+        if (!descs) return fail(TV_ERR_INVALID_ARG, "the per-tet path needs host descriptors");
         tv::StageScope sc(tv::kStageVoxelize, s);
-        for (const tv::MeshDesc &d : descs) {
+        for (const tv::MeshDesc &d : *descs) {
             if (!accumulate) tv::launch_clear(d.grid, (int64_t)d.g.n[0] * d.g.n[1] * d.g.words, s);
             tv::launch_voxelize_per_tet(d, b, strict, s);
         }
@@ -219,6 +239,31 @@ tv_status run_impl(std::vector<tv::MeshDesc> &descs, const tv::CallSizes &c, uin
     return check_hip("voxelize launch");
 }
 
+// The whole call for final descriptors: table upload (batch calls), then
+// the launch sequence.
+tv_status run_impl(std::vector<tv::MeshDesc> &descs, const tv::CallSizes &c, uint8_t *ws,
+                   hipStream_t s, uint32_t flags) {
+    if (c.table) {
+        const tv_status st = upload_table(descs, c, ws, s);
+        if (st) return st;
+    }
+    const tv::MeshTable T = make_table(c, ws, descs.data(), flags);
+    return enqueue(T, c, ws, s, flags, &descs);
+}
+
+// Consistency tag of a batch plan (catches plans not made by
+// tv_batch_prepare, or edited since).
+uint32_t plan_check(const tv_batch_plan &p) {
+    uint64_t h = 0x9e3779b97f4a7c15ull;
+    const uint64_t v[6] = {(uint64_t)p.meshes, (uint64_t)p.nv, (uint64_t)p.nt, (uint64_t)p.ntiles,
+                           p.ws, (uint64_t)p.flags};
+    for (uint64_t x : v) {
+        h ^= x + 0x9e3779b97f4a7c15ull + (h << 6) + (h >> 2);
+        h *= 0xff51afd7ed558ccdull;
+    }
+    return (uint32_t)(h ^ (h >> 32)) | 1u;
+}
+
 tv_status check_ws(void *ws, size_t ws_bytes, size_t need, uint32_t flags) {
     if (flags & ~kKnownFlags) return fail(TV_ERR_INVALID_ARG, "unknown flag bits 0x%x", flags);
     if (!ws || ((uintptr_t)ws & 255u))
@@ -236,7 +281,7 @@ tv_status voxelize_one(const void *verts, uint32_t fmt, int64_t nv, const int32_
     if ((st = check_ws(ws, ws_bytes, tv_workspace_bytes(nv, nt, dims, flags), flags))) return st;
     std::vector<tv::MeshDesc> descs(
         1, make_desc_impl(verts, fmt, nv, tets, nt, dims, bbox, grid, kMinTilesSingle));
-    const tv::CallSizes c = assign_bases_impl(descs);
+    const tv::CallSizes c = assign_bases_impl(descs, false);
     return run_impl(descs, c, static_cast<uint8_t *>(ws), reinterpret_cast<hipStream_t>(stream), flags);
 }
 
@@ -271,7 +316,9 @@ MeshDesc make_batch_desc(const void *verts, uint32_t fmt, int64_t nv, const int3
     return make_desc_impl(verts, fmt, nv, tets, nt, dims, bbox, grid, kMinTilesBatch);
 }
 
-CallSizes assign_bases(std::vector<MeshDesc> &descs) { return assign_bases_impl(descs); }
+CallSizes assign_bases(std::vector<MeshDesc> &descs) {
+    return assign_bases_impl(descs, descs.size() > 1);
+}
 
 tv_status run_meshes(std::vector<MeshDesc> &descs, const CallSizes &c, uint8_t *ws, hipStream_t s,
                      uint32_t flags) {
@@ -322,7 +369,7 @@ size_t tv_batch_workspace_bytes(const tv_mesh *meshes, int32_t n, uint32_t flags
     std::vector<tv::MeshDesc> descs;
     tv_status st;
     if (!batch_descs(meshes, n, descs, st)) return 0;
-    return tv::layout(assign_bases_impl(descs)).total;
+    return tv::layout(assign_bases_impl(descs, true)).total;
 }
 
 tv_status tv_voxelize_batch(const tv_mesh *meshes, int32_t n, void *ws, size_t ws_bytes,
@@ -331,10 +378,48 @@ tv_status tv_voxelize_batch(const tv_mesh *meshes, int32_t n, void *ws, size_t w
     std::vector<tv::MeshDesc> descs;
     tv_status st;
     if (!batch_descs(meshes, n, descs, st)) return st;
-    const tv::CallSizes c = assign_bases_impl(descs);
+    const tv::CallSizes c = assign_bases_impl(descs, true);
     if (c.nt > kMaxTets) return fail(TV_ERR_INVALID_ARG, "batch has more than 2^28 tets");
     if ((st = check_ws(ws, ws_bytes, tv::layout(c).total, flags))) return st;
     return run_impl(descs, c, static_cast<uint8_t *>(ws), reinterpret_cast<hipStream_t>(stream), flags);
+}
+
+tv_status tv_batch_prepare(const tv_mesh *meshes, int32_t n, void *ws, size_t ws_bytes,
+                           void *stream, uint32_t flags, tv_batch_plan *plan) {
+    if (!plan) return fail(TV_ERR_INVALID_ARG, "plan is null");
+    memset(plan, 0, sizeof *plan);
+    if (!meshes || n <= 0) return fail(TV_ERR_INVALID_ARG, "empty batch");
+    if (flags & TV_PATH_PER_TET)
+        return fail(TV_ERR_INVALID_ARG, "the per-tet path is not available for a prepared batch");
+    std::vector<tv::MeshDesc> descs;
+    tv_status st;
+    if (!batch_descs(meshes, n, descs, st)) return st;
+    const tv::CallSizes c = assign_bases_impl(descs, true);
+    if (c.nt > kMaxTets) return fail(TV_ERR_INVALID_ARG, "batch has more than 2^28 tets");
+    if ((st = check_ws(ws, ws_bytes, tv::layout(c).total, flags))) return st;
+    if ((st = upload_table(descs, c, static_cast<uint8_t *>(ws), reinterpret_cast<hipStream_t>(stream))))
+        return st;
+    plan->meshes = c.meshes;
+    plan->nv = c.nv;
+    plan->nt = c.nt;
+    plan->ntiles = c.ntiles;
+    plan->ws = (uint64_t)(uintptr_t)ws;
+    plan->flags = flags;
+    plan->check = plan_check(*plan);
+    return TV_OK;
+}
+
+tv_status tv_batch_run(const tv_batch_plan *plan, void *ws, size_t ws_bytes, void *stream) {
+    if (!plan || plan->check != plan_check(*plan) || plan->meshes <= 0)
+        return fail(TV_ERR_INVALID_ARG, "not a plan filled by tv_batch_prepare");
+    if (plan->ws != (uint64_t)(uintptr_t)ws)
+        return fail(TV_ERR_INVALID_ARG, "the plan belongs to another workspace");
+    const tv::CallSizes c = {plan->meshes, plan->nv, plan->nt, plan->ntiles, true};
+    tv_status st;
+    if ((st = check_ws(ws, ws_bytes, tv::layout(c).total, plan->flags))) return st;
+    uint8_t *w = static_cast<uint8_t *>(ws);
+    const tv::MeshTable T = make_table(c, w, nullptr, plan->flags);
+    return enqueue(T, c, w, reinterpret_cast<hipStream_t>(stream), plan->flags, nullptr);
 }
 
 tv_status tv_voxelize_pipelined(const float *verts_host, int64_t nv, const int32_t *tets_host,

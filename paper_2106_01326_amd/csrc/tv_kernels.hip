@@ -39,7 +39,7 @@ __device__ __forceinline__ int32_t find_mesh(const int64_t *__restrict__ pre, in
 }
 
 __device__ __forceinline__ const MeshDesc &mesh_desc(const MeshTable &T, int32_t m) {
-    return T.n == 1 ? T.one : T.descs[m];
+    return T.descs ? T.descs[m] : T.one;
 }
 
 // Mesh of global index x for the threads of one workgroup whose indices are

@@ -53,6 +53,9 @@ inline TilePlan plan_tiles(tv_dims d, int64_t min_tiles) {
 struct CallSizes {
     int64_t meshes;
     int64_t nv, nt, ntiles;  // totals over the meshes
+    // the descriptors live in a device table inside the workspace (batch
+    // calls); otherwise a single mesh's descriptor is a kernel argument
+    bool table = false;
 };
 
 struct WorkspaceLayout {
@@ -94,9 +97,9 @@ inline WorkspaceLayout layout(const CallSizes &c) {
     L.chunk_off = off;
     off = align256(off + 4 * ((size_t)c.ntiles + 1));
     L.descs = off;
-    L.descs_bytes = c.meshes > 1 ? sizeof(MeshDesc) * (size_t)c.meshes +
-                                       3 * sizeof(int64_t) * ((size_t)c.meshes + 1)
-                                 : 0;
+    L.descs_bytes = c.table ? sizeof(MeshDesc) * (size_t)c.meshes +
+                                  3 * sizeof(int64_t) * ((size_t)c.meshes + 1)
+                            : 0;
     off = align256(off + L.descs_bytes);
     L.q4 = off;
     off = align256(off + 16 * (size_t)c.nv);

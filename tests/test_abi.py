@@ -89,3 +89,32 @@ def test_batch_host_errors_name_the_mesh(lib):
     assert need > 0
     assert lib.tv_voxelize_batch(ctypes.cast(arr2, P), 2, P(256), need - 256, None, 0) == tv.TV_ERR_WORKSPACE
     assert lib.tv_voxelize_batch(ctypes.cast(arr2, P), 0, P(256), need, None, 0) == tv.TV_ERR_INVALID_ARG
+
+
+def test_batch_prepare_and_run_host_errors(lib):
+    """tv_batch_prepare / tv_batch_run: every argument error is caught on the
+    host before anything is enqueued."""
+    P = ctypes.c_void_p
+    box = tv.BBox((ctypes.c_float * 3)(0, 0, 0), (ctypes.c_float * 3)(1, 1, 1))
+    good = tv.MeshC(256, tv.VERTS_F32, 4, 256, 1, tv.Dims(8, 8, 8), box, 256)
+    bad = tv.MeshC(256, tv.VERTS_F32, 4, 256, 1, tv.Dims(8, 8, 24), box, 256)
+    arr = (tv.MeshC * 2)(good, good)
+    need = lib.tv_batch_workspace_bytes(ctypes.cast(arr, P), 2, 0)
+    plan = tv.BatchPlanC()
+    prep = lambda a, n, ws, nbytes, flags, pl: lib.tv_batch_prepare(ctypes.cast(a, P), n, P(ws), nbytes, None,
+                                                                    flags, pl)
+    assert prep(arr, 2, 256, need, 0, None) == tv.TV_ERR_INVALID_ARG  # no plan
+    assert prep(arr, 0, 256, need, 0, ctypes.byref(plan)) == tv.TV_ERR_INVALID_ARG
+    assert prep(arr, 2, 256, need, tv.PATH_PER_TET, ctypes.byref(plan)) == tv.TV_ERR_INVALID_ARG
+    assert b"per-tet" in lib.tv_last_error()
+    assert prep(arr, 2, 256, need - 256, 0, ctypes.byref(plan)) == tv.TV_ERR_WORKSPACE
+    assert prep(arr, 2, 0, need, 0, ctypes.byref(plan)) == tv.TV_ERR_WORKSPACE
+    assert prep((tv.MeshC * 2)(good, bad), 2, 256, need, 0, ctypes.byref(plan)) == tv.TV_ERR_UNSUPPORTED_DIMS
+    assert b"mesh 1" in lib.tv_last_error()
+    assert plan.check == 0  # a failed prepare leaves no usable plan
+    # a plan that tv_batch_prepare did not fill (or that was edited) is refused
+    assert lib.tv_batch_run(ctypes.byref(plan), P(256), need, None) == tv.TV_ERR_INVALID_ARG
+    forged = tv.BatchPlanC(2, 8, 2, 2, 256, 0, 12345)
+    assert lib.tv_batch_run(ctypes.byref(forged), P(256), need, None) == tv.TV_ERR_INVALID_ARG
+    assert b"tv_batch_prepare" in lib.tv_last_error()
+    assert lib.tv_batch_run(None, P(256), need, None) == tv.TV_ERR_INVALID_ARG

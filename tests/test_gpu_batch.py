@@ -127,3 +127,63 @@ def test_whole_grid_meshes_check_their_tets(oracle_mod):
             q = oracle_mod.snap(np.where(np.isnan(nanv), 0, nanv), *m.bbox)
             want = oracle_mod.voxelize_q(q, m.tets[keep], m.dims)
         assert np.array_equal(to_numpy_words(grids[i]), want), f"mesh {i}"
+
+
+def test_single_mesh_batch(oracle_mod):
+    """A batch of one mesh keeps its descriptor in the workspace table like
+    any batch; the grid equals the oracle's and the single-mesh call's."""
+    import paper_2106_01326_amd as tv
+
+    m = synth.make_mesh(20, 0.35, 64, "ellipsoids", 3, 7201)
+    banner("batch of one mesh")
+    b = tv.Batch([to_item(m)])
+    b.grids[0].fill_(-1)
+    want = oracle_mod.voxelize_mesh(m)
+    assert np.array_equal(to_numpy_words(b.run()[0]), want)
+    b.prepare()
+    b.grids[0].fill_(-1)
+    assert np.array_equal(to_numpy_words(b.run_prepared()[0]), want)
+    assert b.status(0) == tv.TV_OK
+
+
+def test_prepared_batch_runs(oracle_mod, uneven):
+    """tv_batch_prepare once, tv_batch_run many times: every run equals the
+    oracle; a run sees the buffers' current contents; the plan only works
+    with its own workspace."""
+    import ctypes
+
+    import torch
+
+    import paper_2106_01326_amd as tv
+
+    ms = uneven[:20] + uneven[-4:]
+    banner(f"prepared batch of {len(ms)} meshes")
+    items = [to_item(m) for m in ms]
+    b = tv.Batch(items)
+    b.prepare()
+    for r in range(2):
+        for g in b.grids:
+            g.fill_(-1)
+        grids = b.run_prepared()
+        for i, (m, g) in enumerate(zip(ms, grids)):
+            assert np.array_equal(to_numpy_words(g), oracle_mod.voxelize_mesh(m)), f"run {r} mesh {i}"
+            assert b.status(i) == tv.TV_OK
+    # strict mode through its own plan
+    b.prepare(strict=True)
+    for i, (m, g) in enumerate(zip(ms, b.run_prepared())):
+        assert np.array_equal(to_numpy_words(g), oracle_mod.voxelize_mesh(m, mode=oracle_mod.STRICT)), f"mesh {i}"
+    # new vertex contents in place (same topology): the next run uses them
+    b.prepare()
+    k = 3
+    m = ms[k]
+    moved = synth.Mesh(tets=m.tets, dims=m.dims, bbox=m.bbox,
+                       verts=(0.5 + 0.8 * (m.verts - 0.5)).astype(np.float32))
+    items[k][0].copy_(torch.from_numpy(moved.verts).cuda())
+    grids = b.run_prepared()
+    assert np.array_equal(to_numpy_words(grids[k]), oracle_mod.voxelize_mesh(moved))
+    assert np.array_equal(to_numpy_words(grids[0]), oracle_mod.voxelize_mesh(ms[0]))
+    # the plan names its workspace: another one is refused before anything runs
+    other = tv.alloc_workspace(b.workspace.numel())
+    lib = tv.load_library()
+    st = lib.tv_batch_run(ctypes.byref(b.plan), ctypes.c_void_p(other.data_ptr()), other.numel(), None)
+    assert st == tv.TV_ERR_INVALID_ARG and b"another workspace" in lib.tv_last_error()

@@ -58,3 +58,33 @@ def test_unpack_graph_replays():
         g.replay()
         torch.cuda.synchronize()
         assert np.array_equal(out.cpu().numpy(), G.unpack(words, dims)), f"replay {r}"
+
+
+def test_prepared_batch_graph_replays(oracle_mod):
+    """tv_batch_run enqueues kernels only: a captured run replays to the
+    oracle's grids for every mesh, with eager work between replays."""
+    import torch
+
+    import paper_2106_01326_amd as tv
+
+    ms = synth.workload_batch(first=16, workers=1)
+    ms.append(synth.make_mesh(24, 0.3, 128, "ellipsoids", 3, 8003))
+    want = [oracle_mod.voxelize_mesh(m) for m in ms]
+    items = [(torch.from_numpy(m.verts).cuda(), torch.from_numpy(m.tets).cuda(), m.dims, m.bbox, False)
+             for m in ms]
+    b = tv.Batch(items)
+    b.prepare()
+    b.run_prepared()  # eager warm-up
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        b.run_prepared()
+    for r in range(4):
+        for grid in b.grids:
+            grid.fill_(-1)  # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for i, grid in enumerate(b.grids):
+            assert np.array_equal(grid.cpu().numpy().view(np.uint32), want[i]), f"replay {r} mesh {i}"
+            assert b.status(i) == tv.TV_OK
