@@ -196,6 +196,27 @@ def bench_batch(args, torch, tv):
     log(f"batched: {ms_batch:.3f} ms per batch; profiled stages (ms per call) "
         f"{ {k: round(v_ / max(calls, 1), 4) for k, v_ in stages.items()} }")
 
+    # the same batch prepared once and replayed as a captured HIP graph
+    # (tv_batch_prepare, then tv_batch_run inside torch's graph capture)
+    ref = [g.clone() for g in batch.grids]
+    batch.prepare()
+    batch.run_prepared()
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        batch.run_prepared()
+    graph.replay()
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        graph.replay()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_graph = ev0.elapsed_time(ev1) / args.steps
+    graph_same = all(torch.equal(a, b) for a, b in zip(ref, batch.grids))
+    del graph, ref
+    log(f"graph replay of the prepared batch: {ms_graph:.3f} ms per batch; identical={graph_same}")
+
     # per-mesh loop with preallocated grids and workspaces
     grids = [tv.alloc_grid(m.dims, dev) for m in meshes]
     wss = [tv.alloc_workspace(tv.workspace_bytes(m.nv, m.nt, m.dims), dev) for m in meshes]
@@ -228,6 +249,8 @@ def bench_batch(args, torch, tv):
            "per_mesh_loop": {"meshes_per_s": len(meshes) / (ms_loop * 1e-3), "ms_per_pass": ms_loop,
                              "host_wall_ms_per_pass": wall_loop},
            "batched_over_per_mesh": ms_loop / ms_batch, "bit_identical_to_per_mesh": bool(same),
+           "graph_replay": {"ms_per_batch": ms_graph, "meshes_per_s": len(meshes) / (ms_graph * 1e-3),
+                            "bit_identical": bool(graph_same)},
            "stage_ms": {k: v_ / max(calls, 1) for k, v_ in stages.items()}}
     out["roofline"] = tile_roofline(torch, tv, items, meshes, stages.get("voxelize", 0.0) / max(calls, 1))
     if not args.no_cpu_baseline:

@@ -180,12 +180,46 @@ typedef struct {
     int64_t meshes, nv, nt, ntiles; /* totals of the prepared batch */
     uint64_t ws;                    /* address of the workspace holding the table */
     uint32_t flags;                 /* flags given to tv_batch_prepare */
+    int32_t launch[4];              /* launch parameters in force at prepare time */
     uint32_t check;                 /* consistency tag */
 } tv_batch_plan;
 
 tv_status tv_batch_prepare(const tv_mesh *meshes, int32_t n, void *ws, size_t ws_bytes,
                            void *stream, uint32_t flags, tv_batch_plan *plan);
 tv_status tv_batch_run(const tv_batch_plan *plan, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Launch parameters of the tile pipeline, one set for single-mesh calls
+ * (tv_voxelize, tv_voxelize_q, tv_voxelize_pipelined) and one for batch
+ * calls.  They change speed only: every valid setting gives the same grids
+ * bit for bit.  (They are this library's work decomposition, not the
+ * paper's: Section 3 tests each tet's bounding-box candidates, and every
+ * setting still does exactly that.)
+ *   tile_cols_log2  largest tile edge in columns, log2, in [3, 5]
+ *   min_tiles       tiles are halved (down to 8 x 8 columns) while a grid
+ *                   has fewer than this, in [1, 2^20]
+ *   chunk_pieces    (tet, tile) pieces per work-queue task, in [64, 65536]
+ *   strip_columns   kept columns per lane task, in [1, 64]
+ *   piece_cap       tets meeting more tiles take the per-tet large path, [1, 8]
+ *   wgs_per_cu      persistent tile workgroups per compute unit, in [1, 8]
+ * Defaults (tv_default_params): single {5, 512, 4096, 8, 8, 2}, batch
+ * {5, 1, 4096, 8, 8, 2}.  tv_set_params validates all fields
+ * (TV_ERR_INVALID_ARG, nothing changed) and with p == NULL restores the
+ * defaults.  The settings are process-wide; each call copies them when it
+ * starts, so set them before enqueueing work.  Workspace sizes depend on
+ * the tile fields: query tv_*_workspace_bytes after a change.  A prepared
+ * batch keeps the parameters of its tv_batch_prepare call.  The server
+ * always uses the batch defaults.  The autotuner that picks them lives in
+ * the Python package (timings on the device, a JSON cache).
+ */
+typedef struct {
+    int32_t tile_cols_log2, min_tiles, chunk_pieces, strip_columns, piece_cap, wgs_per_cu;
+} tv_params;
+#define TV_PARAMS_SINGLE 0
+#define TV_PARAMS_BATCH 1
+tv_status tv_default_params(int32_t which, tv_params *out);
+tv_status tv_get_params(int32_t which, tv_params *out);
+tv_status tv_set_params(int32_t which, const tv_params *p);
 
 /*
  * Snap only: fp32 world coordinates verts [nv][3] -> lattice coordinates

@@ -41,6 +41,7 @@ VERTS_Q32 = 1
 
 EXPORTED = ("tv_grid_words", "tv_workspace_bytes", "tv_voxelize", "tv_voxelize_q", "tv_snap",
             "tv_batch_workspace_bytes", "tv_voxelize_batch", "tv_batch_prepare", "tv_batch_run",
+            "tv_default_params", "tv_get_params", "tv_set_params",
             "tv_fetch_status", "tv_status_string", "tv_last_error", "tv_profile_enable",
             "tv_profile_read", "tv_profile_stage_name", "tv_server_create", "tv_server_submit",
             "tv_server_poll", "tv_server_wait", "tv_server_result", "tv_server_copy_grid",
@@ -77,7 +78,16 @@ class MeshC(ctypes.Structure):
 class BatchPlanC(ctypes.Structure):
     _fields_ = [("meshes", ctypes.c_int64), ("nv", ctypes.c_int64), ("nt", ctypes.c_int64),
                 ("ntiles", ctypes.c_int64), ("ws", ctypes.c_uint64), ("flags", ctypes.c_uint32),
-                ("check", ctypes.c_uint32)]
+                ("launch", ctypes.c_int32 * 4), ("check", ctypes.c_uint32)]
+
+
+PARAM_FIELDS = ("tile_cols_log2", "min_tiles", "chunk_pieces", "strip_columns", "piece_cap", "wgs_per_cu")
+PARAMS_SINGLE = 0
+PARAMS_BATCH = 1
+
+
+class ParamsC(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int32) for f in PARAM_FIELDS]
 
 
 class HostMeshC(ctypes.Structure):
@@ -161,6 +171,9 @@ def load_library():
     lib.tv_batch_prepare.restype = st
     lib.tv_batch_run.argtypes = [ctypes.POINTER(BatchPlanC), P, ctypes.c_size_t, P]
     lib.tv_batch_run.restype = st
+    for name in ("tv_default_params", "tv_get_params", "tv_set_params"):
+        getattr(lib, name).argtypes = [ctypes.c_int32, ctypes.POINTER(ParamsC)]
+        getattr(lib, name).restype = st
     lib.tv_snap.argtypes = [P, i64, BBox, P, P]
     lib.tv_snap.restype = st
     lib.tv_fetch_status.argtypes = [P, ctypes.c_int32, P]
@@ -520,6 +533,48 @@ def _mesh_struct(verts, tets, dims, bbox, grid, qverts):
                  _bbox(bbox), gptr.value)
 
 
+def _params_which(which):
+    if which in ("single", PARAMS_SINGLE):
+        return PARAMS_SINGLE
+    if which in ("batch", PARAMS_BATCH):
+        return PARAMS_BATCH
+    raise ValueError(f"params set {which!r}: 'single' or 'batch'")
+
+
+def default_params(which="single"):
+    """The library's default launch parameters (tv_default_params) as a dict."""
+    p = ParamsC()
+    _check(load_library().tv_default_params(_params_which(which), ctypes.byref(p)))
+    return {f: int(getattr(p, f)) for f in PARAM_FIELDS}
+
+
+def get_params(which="single"):
+    """Launch parameters in force (tv_get_params) as a dict."""
+    p = ParamsC()
+    _check(load_library().tv_get_params(_params_which(which), ctypes.byref(p)))
+    return {f: int(getattr(p, f)) for f in PARAM_FIELDS}
+
+
+def set_params(which="single", params=None, **fields):
+    """Sets launch parameters (tv_set_params): ``params`` (a dict) updated by
+    ``fields``, over the current values; ``set_params(which, None)`` with no
+    fields restores the defaults.  Returns the previous setting."""
+    lib = load_library()
+    w = _params_which(which)
+    old = get_params(which)
+    if params is None and not fields:
+        _check(lib.tv_set_params(w, None))
+        return old
+    new = dict(old)
+    new.update(params or {})
+    new.update(fields)
+    unknown = set(new) - set(PARAM_FIELDS)
+    if unknown:
+        raise ValueError(f"unknown parameters {sorted(unknown)}")
+    _check(lib.tv_set_params(w, ctypes.byref(ParamsC(*[int(new[f]) for f in PARAM_FIELDS]))))
+    return old
+
+
 class Batch:
     """A prepared batch: device tensors of many meshes and their descriptor
     array, reusable across calls (the grids are overwritten each call)."""
@@ -548,6 +603,16 @@ class Batch:
                                      ctypes.c_void_p(self.workspace.data_ptr()), self.workspace.numel(),
                                      _stream_handle(stream), flags))
         return self.grids
+
+    def resize_workspace(self):
+        """Grows the workspace if the batch parameters in force need more."""
+        need = int(load_library().tv_batch_workspace_bytes(ctypes.cast(self.array, ctypes.c_void_p), self.n, 0))
+        if need == 0:
+            _check(TV_ERR_INVALID_ARG)
+        if self.workspace.numel() < need:
+            self.workspace = alloc_workspace(need, self.workspace.device)
+            self.plan = None
+        return self.workspace
 
     def prepare(self, strict=False, accumulate=False, stream=None):
         """Uploads the descriptor table into the workspace (tv_batch_prepare);

@@ -7,6 +7,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <vector>
 
 #include "tv.h"
@@ -19,10 +20,16 @@ namespace {
 
 thread_local char g_last_error[256] = "";
 
-// Tiles wanted per lone grid before tiles are made smaller (independent of
-// the device so that workspace sizes do not depend on it).
-constexpr int64_t kMinTilesSingle = 512;
-constexpr int64_t kMinTilesBatch = 1;
+// Launch parameters in force for single-mesh calls ([0]) and batch calls
+// ([1]); each call takes a copy when it starts.  (They do not depend on the
+// device, so neither do workspace sizes.)
+std::mutex g_params_mu;
+tv::Params g_params[2] = {tv::kDefaultSingle, tv::kDefaultBatch};
+
+tv::Params current_params(int which) {
+    std::lock_guard<std::mutex> lk(g_params_mu);
+    return g_params[which];
+}
 
 tv_status fail(tv_status code, const char *fmt, ...) {
     va_list ap;
@@ -98,7 +105,7 @@ tv_status check_mesh_impl(const void *verts, uint32_t fmt, int64_t nv, const int
 
 tv::MeshDesc make_desc_impl(const void *verts, uint32_t fmt, int64_t nv, const int32_t *tets,
                        int64_t nt, tv_dims dims, const tv_bbox *bbox, uint32_t *grid,
-                       int64_t min_tiles) {
+                       const tv::Params &P) {
     tv::MeshDesc d;
     memset(&d, 0, sizeof d);
     d.verts = verts;
@@ -107,7 +114,7 @@ tv::MeshDesc make_desc_impl(const void *verts, uint32_t fmt, int64_t nv, const i
     d.nv = nv;
     d.nt = nt;
     d.g = make_geom(dims);
-    d.p = tv::plan_tiles(dims, min_tiles);
+    d.p = tv::plan_tiles(dims, P.min_tiles, P.tile_cols_log2);
     d.fmt = fmt == TV_VERTS_F32 ? tv::kFmtF32 : tv::kFmtQ32;
     if (fmt == TV_VERTS_F32) {
         for (int a = 0; a < 3; ++a) {
@@ -158,14 +165,14 @@ tv_status upload_table(const std::vector<tv::MeshDesc> &descs, const tv::CallSiz
 // Kernel-side view of a call: the descriptor table in the workspace, or the
 // single descriptor `one` passed by value.
 tv::MeshTable make_table(const tv::CallSizes &c, uint8_t *ws, const tv::MeshDesc *one,
-                         uint32_t flags) {
+                         uint32_t flags, const tv::Params &P) {
     const tv::WorkspaceLayout L = tv::layout(c);
     tv::MeshTable T;
     memset(&T, 0, sizeof T);
     T.n = (int32_t)c.meshes;
-    T.chunk = tv::kChunkPieces;
-    T.strip = tv::kStripColumns;
-    T.piece_cap = tv::kPieceCap;
+    T.chunk = P.chunk;
+    T.strip = P.strip;
+    T.piece_cap = P.piece_cap;
     T.accumulate = (flags & TV_ACCUMULATE) ? 1 : 0;
     T.nv_total = c.nv;
     T.nt_total = c.nt;
@@ -187,7 +194,7 @@ tv::MeshTable make_table(const tv::CallSizes &c, uint8_t *ws, const tv::MeshDesc
 // The launch sequence: kernels only (no host copies, memsets or
 // allocations).  `descs` is needed by the per-tet reference path only.
 tv_status enqueue(const tv::MeshTable &T, const tv::CallSizes &c, uint8_t *ws, hipStream_t s,
-                  uint32_t flags, const std::vector<tv::MeshDesc> *descs) {
+                  uint32_t flags, const std::vector<tv::MeshDesc> *descs, int wgs_per_cu) {
     const tv::WorkspaceLayout L = tv::layout(c);
     const tv::BinBuffers b = tv::bin_buffers(ws, L);
     const bool strict = (flags & TV_TIE_STRICT) != 0;
@@ -230,7 +237,7 @@ tv_status enqueue(const tv::MeshTable &T, const tv::CallSizes &c, uint8_t *ws, h
     const int cus = device_cus();
     {
         tv::StageScope sc(tv::kStageVoxelize, s);
-        tv::launch_tile_voxelize(T, b, strict, 2 * cus, s);
+        tv::launch_tile_voxelize(T, b, strict, wgs_per_cu * cus, s);
     }
     {
         tv::StageScope sc(tv::kStageLarge, s);
@@ -242,21 +249,33 @@ tv_status enqueue(const tv::MeshTable &T, const tv::CallSizes &c, uint8_t *ws, h
 // The whole call for final descriptors: table upload (batch calls), then
 // the launch sequence.
 tv_status run_impl(std::vector<tv::MeshDesc> &descs, const tv::CallSizes &c, uint8_t *ws,
-                   hipStream_t s, uint32_t flags) {
+                   hipStream_t s, uint32_t flags, const tv::Params &P) {
     if (c.table) {
         const tv_status st = upload_table(descs, c, ws, s);
         if (st) return st;
     }
-    const tv::MeshTable T = make_table(c, ws, descs.data(), flags);
-    return enqueue(T, c, ws, s, flags, &descs);
+    const tv::MeshTable T = make_table(c, ws, descs.data(), flags, P);
+    return enqueue(T, c, ws, s, flags, &descs, P.wgs_per_cu);
+}
+
+// Workspace bytes of a single-mesh call under parameters P.
+size_t single_ws_bytes(int64_t nv, int64_t nt, tv_dims dims, const tv::Params &P) {
+    tv::CallSizes c = {1, nv, nt, tv::plan_tiles(dims, P.min_tiles, P.tile_cols_log2).ntiles};
+    return tv::layout(c).total;
 }
 
 // Consistency tag of a batch plan (catches plans not made by
 // tv_batch_prepare, or edited since).
 uint32_t plan_check(const tv_batch_plan &p) {
     uint64_t h = 0x9e3779b97f4a7c15ull;
-    const uint64_t v[6] = {(uint64_t)p.meshes, (uint64_t)p.nv, (uint64_t)p.nt, (uint64_t)p.ntiles,
-                           p.ws, (uint64_t)p.flags};
+    const uint64_t v[8] = {(uint64_t)p.meshes,
+                           (uint64_t)p.nv,
+                           (uint64_t)p.nt,
+                           (uint64_t)p.ntiles,
+                           p.ws,
+                           (uint64_t)p.flags,
+                           (uint64_t)(uint32_t)p.launch[0] << 32 | (uint32_t)p.launch[1],
+                           (uint64_t)(uint32_t)p.launch[2] << 32 | (uint32_t)p.launch[3]};
     for (uint64_t x : v) {
         h ^= x + 0x9e3779b97f4a7c15ull + (h << 6) + (h >> 2);
         h *= 0xff51afd7ed558ccdull;
@@ -278,15 +297,16 @@ tv_status voxelize_one(const void *verts, uint32_t fmt, int64_t nv, const int32_
                        void *stream, uint32_t flags) {
     tv_status st = check_mesh_impl(verts, fmt, nv, tets, nt, dims, bbox, grid, "");
     if (st) return st;
-    if ((st = check_ws(ws, ws_bytes, tv_workspace_bytes(nv, nt, dims, flags), flags))) return st;
-    std::vector<tv::MeshDesc> descs(
-        1, make_desc_impl(verts, fmt, nv, tets, nt, dims, bbox, grid, kMinTilesSingle));
+    const tv::Params P = current_params(0);
+    if ((st = check_ws(ws, ws_bytes, single_ws_bytes(nv, nt, dims, P), flags))) return st;
+    std::vector<tv::MeshDesc> descs(1, make_desc_impl(verts, fmt, nv, tets, nt, dims, bbox, grid, P));
     const tv::CallSizes c = assign_bases_impl(descs, false);
-    return run_impl(descs, c, static_cast<uint8_t *>(ws), reinterpret_cast<hipStream_t>(stream), flags);
+    return run_impl(descs, c, static_cast<uint8_t *>(ws), reinterpret_cast<hipStream_t>(stream), flags,
+                    P);
 }
 
-bool batch_descs(const tv_mesh *meshes, int32_t n, std::vector<tv::MeshDesc> &descs,
-                 tv_status &st) {
+bool batch_descs(const tv_mesh *meshes, int32_t n, const tv::Params &P,
+                 std::vector<tv::MeshDesc> &descs, tv_status &st) {
     descs.clear();
     descs.reserve((size_t)n);
     char which[48];
@@ -296,7 +316,7 @@ bool batch_descs(const tv_mesh *meshes, int32_t n, std::vector<tv::MeshDesc> &de
         st = check_mesh_impl(m.verts, m.vert_format, m.nv, m.tets, m.nt, m.dims, &m.bbox, m.grid, which);
         if (st) return false;
         descs.push_back(make_desc_impl(m.verts, m.vert_format, m.nv, m.tets, m.nt, m.dims, &m.bbox,
-                                  m.grid, kMinTilesBatch));
+                                       m.grid, P));
     }
     st = TV_OK;
     return true;
@@ -313,7 +333,7 @@ tv_status check_mesh(const void *verts, uint32_t fmt, int64_t nv, const int32_t 
 
 MeshDesc make_batch_desc(const void *verts, uint32_t fmt, int64_t nv, const int32_t *tets,
                          int64_t nt, tv_dims dims, const tv_bbox *bbox, uint32_t *grid) {
-    return make_desc_impl(verts, fmt, nv, tets, nt, dims, bbox, grid, kMinTilesBatch);
+    return make_desc_impl(verts, fmt, nv, tets, nt, dims, bbox, grid, kDefaultBatch);
 }
 
 CallSizes assign_bases(std::vector<MeshDesc> &descs) {
@@ -322,7 +342,7 @@ CallSizes assign_bases(std::vector<MeshDesc> &descs) {
 
 tv_status run_meshes(std::vector<MeshDesc> &descs, const CallSizes &c, uint8_t *ws, hipStream_t s,
                      uint32_t flags) {
-    return run_impl(descs, c, ws, s, flags);
+    return run_impl(descs, c, ws, s, flags, kDefaultBatch);
 }
 
 tv_status set_error(tv_status code, const char *fmt, ...) {
@@ -345,8 +365,7 @@ size_t tv_grid_words(tv_dims d) {
 size_t tv_workspace_bytes(int64_t nv, int64_t nt, tv_dims dims, uint32_t flags) {
     (void)flags;
     if (nv < 0 || nt < 0 || !tv_grid_words(dims)) return 0;
-    const tv::CallSizes c = {1, nv, nt, tv::plan_tiles(dims, kMinTilesSingle).ntiles};
-    return tv::layout(c).total;
+    return single_ws_bytes(nv, nt, dims, current_params(0));
 }
 
 tv_status tv_voxelize(const float *verts, int64_t nv, const int32_t *tets, int64_t nt,
@@ -368,20 +387,63 @@ size_t tv_batch_workspace_bytes(const tv_mesh *meshes, int32_t n, uint32_t flags
     if (!meshes || n <= 0) return 0;
     std::vector<tv::MeshDesc> descs;
     tv_status st;
-    if (!batch_descs(meshes, n, descs, st)) return 0;
+    if (!batch_descs(meshes, n, current_params(1), descs, st)) return 0;
     return tv::layout(assign_bases_impl(descs, true)).total;
 }
 
 tv_status tv_voxelize_batch(const tv_mesh *meshes, int32_t n, void *ws, size_t ws_bytes,
                             void *stream, uint32_t flags) {
     if (!meshes || n <= 0) return fail(TV_ERR_INVALID_ARG, "empty batch");
+    const tv::Params P = current_params(1);
     std::vector<tv::MeshDesc> descs;
     tv_status st;
-    if (!batch_descs(meshes, n, descs, st)) return st;
+    if (!batch_descs(meshes, n, P, descs, st)) return st;
     const tv::CallSizes c = assign_bases_impl(descs, true);
     if (c.nt > kMaxTets) return fail(TV_ERR_INVALID_ARG, "batch has more than 2^28 tets");
     if ((st = check_ws(ws, ws_bytes, tv::layout(c).total, flags))) return st;
-    return run_impl(descs, c, static_cast<uint8_t *>(ws), reinterpret_cast<hipStream_t>(stream), flags);
+    return run_impl(descs, c, static_cast<uint8_t *>(ws), reinterpret_cast<hipStream_t>(stream), flags,
+                    P);
+}
+
+tv_status tv_default_params(int32_t which, tv_params *out) {
+    if (!out || (which != TV_PARAMS_SINGLE && which != TV_PARAMS_BATCH))
+        return fail(TV_ERR_INVALID_ARG, "params: need TV_PARAMS_SINGLE or TV_PARAMS_BATCH and an output");
+    const tv::Params &P = which == TV_PARAMS_SINGLE ? tv::kDefaultSingle : tv::kDefaultBatch;
+    *out = {P.tile_cols_log2, P.min_tiles, P.chunk, P.strip, P.piece_cap, P.wgs_per_cu};
+    return TV_OK;
+}
+
+tv_status tv_get_params(int32_t which, tv_params *out) {
+    if (!out || (which != TV_PARAMS_SINGLE && which != TV_PARAMS_BATCH))
+        return fail(TV_ERR_INVALID_ARG, "params: need TV_PARAMS_SINGLE or TV_PARAMS_BATCH and an output");
+    const tv::Params P = current_params(which);
+    *out = {P.tile_cols_log2, P.min_tiles, P.chunk, P.strip, P.piece_cap, P.wgs_per_cu};
+    return TV_OK;
+}
+
+tv_status tv_set_params(int32_t which, const tv_params *p) {
+    if (which != TV_PARAMS_SINGLE && which != TV_PARAMS_BATCH)
+        return fail(TV_ERR_INVALID_ARG, "params: need TV_PARAMS_SINGLE or TV_PARAMS_BATCH");
+    tv::Params P = which == TV_PARAMS_SINGLE ? tv::kDefaultSingle : tv::kDefaultBatch;
+    if (p) {
+        if (p->tile_cols_log2 < 3 || p->tile_cols_log2 > 5)
+            return fail(TV_ERR_INVALID_ARG, "params: tile_cols_log2 %d not in [3,5]", p->tile_cols_log2);
+        if (p->min_tiles < 1 || p->min_tiles > (1 << 20))
+            return fail(TV_ERR_INVALID_ARG, "params: min_tiles %d not in [1,2^20]", p->min_tiles);
+        if (p->chunk_pieces < 64 || p->chunk_pieces > 65536)
+            return fail(TV_ERR_INVALID_ARG, "params: chunk_pieces %d not in [64,65536]", p->chunk_pieces);
+        if (p->strip_columns < 1 || p->strip_columns > 64)
+            return fail(TV_ERR_INVALID_ARG, "params: strip_columns %d not in [1,64]", p->strip_columns);
+        if (p->piece_cap < 1 || p->piece_cap > tv::kPieceCap)
+            return fail(TV_ERR_INVALID_ARG, "params: piece_cap %d not in [1,%d]", p->piece_cap, tv::kPieceCap);
+        if (p->wgs_per_cu < 1 || p->wgs_per_cu > 8)
+            return fail(TV_ERR_INVALID_ARG, "params: wgs_per_cu %d not in [1,8]", p->wgs_per_cu);
+        P = {p->tile_cols_log2, p->min_tiles, p->chunk_pieces, p->strip_columns, p->piece_cap,
+             p->wgs_per_cu};
+    }
+    std::lock_guard<std::mutex> lk(g_params_mu);
+    g_params[which] = P;
+    return TV_OK;
 }
 
 tv_status tv_batch_prepare(const tv_mesh *meshes, int32_t n, void *ws, size_t ws_bytes,
@@ -391,9 +453,10 @@ tv_status tv_batch_prepare(const tv_mesh *meshes, int32_t n, void *ws, size_t ws
     if (!meshes || n <= 0) return fail(TV_ERR_INVALID_ARG, "empty batch");
     if (flags & TV_PATH_PER_TET)
         return fail(TV_ERR_INVALID_ARG, "the per-tet path is not available for a prepared batch");
+    const tv::Params P = current_params(1);
     std::vector<tv::MeshDesc> descs;
     tv_status st;
-    if (!batch_descs(meshes, n, descs, st)) return st;
+    if (!batch_descs(meshes, n, P, descs, st)) return st;
     const tv::CallSizes c = assign_bases_impl(descs, true);
     if (c.nt > kMaxTets) return fail(TV_ERR_INVALID_ARG, "batch has more than 2^28 tets");
     if ((st = check_ws(ws, ws_bytes, tv::layout(c).total, flags))) return st;
@@ -405,6 +468,10 @@ tv_status tv_batch_prepare(const tv_mesh *meshes, int32_t n, void *ws, size_t ws
     plan->ntiles = c.ntiles;
     plan->ws = (uint64_t)(uintptr_t)ws;
     plan->flags = flags;
+    plan->launch[0] = P.chunk;
+    plan->launch[1] = P.strip;
+    plan->launch[2] = P.piece_cap;
+    plan->launch[3] = P.wgs_per_cu;
     plan->check = plan_check(*plan);
     return TV_OK;
 }
@@ -418,8 +485,14 @@ tv_status tv_batch_run(const tv_batch_plan *plan, void *ws, size_t ws_bytes, voi
     tv_status st;
     if ((st = check_ws(ws, ws_bytes, tv::layout(c).total, plan->flags))) return st;
     uint8_t *w = static_cast<uint8_t *>(ws);
-    const tv::MeshTable T = make_table(c, w, nullptr, plan->flags);
-    return enqueue(T, c, w, reinterpret_cast<hipStream_t>(stream), plan->flags, nullptr);
+    tv::Params P = tv::kDefaultBatch;  // the tile plan is already in the table
+    P.chunk = plan->launch[0];
+    P.strip = plan->launch[1];
+    P.piece_cap = plan->launch[2];
+    P.wgs_per_cu = plan->launch[3];
+    const tv::MeshTable T = make_table(c, w, nullptr, plan->flags, P);
+    return enqueue(T, c, w, reinterpret_cast<hipStream_t>(stream), plan->flags, nullptr,
+                   P.wgs_per_cu);
 }
 
 tv_status tv_voxelize_pipelined(const float *verts_host, int64_t nv, const int32_t *tets_host,

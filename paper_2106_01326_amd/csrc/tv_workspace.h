@@ -12,9 +12,21 @@ namespace tv {
 
 constexpr int32_t kMetaWords = 64;
 constexpr int32_t kMinStatusWords = 64;
-constexpr int32_t kPieceCap = 8;
-constexpr int32_t kChunkPieces = 4096;
-constexpr int32_t kStripColumns = 8;
+constexpr int32_t kPieceCap = 8;  // piece slots reserved per tet (the largest piece_cap)
+
+// Launch parameters of the tile pipeline (tv_params in the C ABI).
+struct Params {
+    int32_t tile_cols_log2;  // largest tile edge in columns, log2 (3..5)
+    int32_t min_tiles;       // tiles are made smaller while a grid has fewer
+    int32_t chunk;           // pieces per work-queue task
+    int32_t strip;           // kept columns per lane task
+    int32_t piece_cap;       // tets meeting more tiles go to the large-tet kernel
+    int32_t wgs_per_cu;      // persistent tile workgroups per compute unit
+};
+// A lone grid wants >= 512 tiles to spread over the chip; batch meshes keep
+// the largest tiles (their parallelism comes from the mesh count).
+constexpr Params kDefaultSingle = {5, 512, 4096, 8, 8, 2};
+constexpr Params kDefaultBatch = {5, 1, 4096, 8, 8, 2};
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -24,17 +36,16 @@ inline int ilog2(int64_t n) {
     return s;
 }
 
-// Tiles of at most 32 x 32 columns x 4 words (16 KiB of LDS bitmap), made
-// smaller (down to 8 x 8 columns) while the grid has fewer than
-// `min_tiles` of them, so that a lone small grid still spreads over the
-// chip.  (Batches pass min_tiles = 1: their parallelism comes from the
-// number of meshes.)
-inline TilePlan plan_tiles(tv_dims d, int64_t min_tiles) {
+// Tiles of at most 2^max_log2 x 2^max_log2 columns (max_log2 <= 5) x 4
+// words (at most 16 KiB of LDS bitmap), made smaller (down to 8 x 8
+// columns) while the grid has fewer than `min_tiles` of them, so that a lone
+// small grid still spreads over the chip.
+inline TilePlan plan_tiles(tv_dims d, int64_t min_tiles, int max_log2) {
     TilePlan p;
     const int W = (d.nz + 31) / 32;
     p.lw = ilog2(W) < 2 ? ilog2(W) : 2;
-    p.lx = ilog2(d.nx) < 5 ? ilog2(d.nx) : 5;
-    p.ly = ilog2(d.ny) < 5 ? ilog2(d.ny) : 5;
+    p.lx = ilog2(d.nx) < max_log2 ? ilog2(d.nx) : max_log2;
+    p.ly = ilog2(d.ny) < max_log2 ? ilog2(d.ny) : max_log2;
     auto count = [&]() {
         return (int64_t)(d.nx >> p.lx) * (int64_t)(d.ny >> p.ly) * (int64_t)(W >> p.lw);
     };

@@ -114,7 +114,55 @@ def test_batch_prepare_and_run_host_errors(lib):
     assert plan.check == 0  # a failed prepare leaves no usable plan
     # a plan that tv_batch_prepare did not fill (or that was edited) is refused
     assert lib.tv_batch_run(ctypes.byref(plan), P(256), need, None) == tv.TV_ERR_INVALID_ARG
-    forged = tv.BatchPlanC(2, 8, 2, 2, 256, 0, 12345)
+    forged = tv.BatchPlanC(meshes=2, nv=8, nt=2, ntiles=2, ws=256, flags=0, check=12345)
     assert lib.tv_batch_run(ctypes.byref(forged), P(256), need, None) == tv.TV_ERR_INVALID_ARG
     assert b"tv_batch_prepare" in lib.tv_last_error()
     assert lib.tv_batch_run(None, P(256), need, None) == tv.TV_ERR_INVALID_ARG
+
+
+def test_launch_parameters(lib):
+    """tv_params: defaults, validation (nothing changes on an error), reset,
+    and workspace sizes that follow the tile fields."""
+    assert tv.default_params("single") == {"tile_cols_log2": 5, "min_tiles": 512, "chunk_pieces": 4096,
+                                           "strip_columns": 8, "piece_cap": 8, "wgs_per_cu": 2}
+    assert tv.default_params("batch")["min_tiles"] == 1
+    try:
+        base = tv.workspace_bytes(1000, 1000, (256, 256, 256))
+        tv.set_params("single", strip_columns=3, chunk_pieces=64, piece_cap=1, wgs_per_cu=8)
+        assert tv.get_params("single")["strip_columns"] == 3
+        assert tv.workspace_bytes(1000, 1000, (256, 256, 256)) == base  # no tile field changed
+        tv.set_params("single", tile_cols_log2=3)  # 8x8-column tiles: more tile counters
+        assert tv.workspace_bytes(1000, 1000, (256, 256, 256)) > base
+        before = tv.get_params("single")
+        for bad in ({"tile_cols_log2": 6}, {"tile_cols_log2": 2}, {"min_tiles": 0}, {"chunk_pieces": 63},
+                    {"strip_columns": 0}, {"strip_columns": 65}, {"piece_cap": 9}, {"wgs_per_cu": 0}):
+            with pytest.raises(tv.TVError):
+                tv.set_params("single", **bad)
+            assert tv.get_params("single") == before
+        assert tv.get_params("batch") == tv.default_params("batch")  # the other set is untouched
+        P = tv.ParamsC()
+        assert lib.tv_get_params(2, ctypes.byref(P)) == tv.TV_ERR_INVALID_ARG
+        assert lib.tv_set_params(-1, None) == tv.TV_ERR_INVALID_ARG
+    finally:
+        tv.set_params("single", None)
+    assert tv.get_params("single") == tv.default_params("single")
+
+
+def test_tune_cache_roundtrip(tmp_path):
+    """The tuner's JSON cache: entries stored by key are applied by key; a
+    missing key changes nothing."""
+    from paper_2106_01326_amd import tune
+
+    path = str(tmp_path / "tune.json")
+    params = dict(tv.default_params("batch"), strip_columns=12, chunk_pieces=2048)
+    tune._store(path, "gfx950:batch:n2^10:nt2^25", {"params": params, "ms_default": 3.7, "ms_best": 3.5})
+    assert tune.cached("gfx950:batch:n2^10:nt2^25", path)["params"] == params
+    try:
+        assert not tune.apply_cached("batch", "gfx950:batch:other", path)
+        assert tv.get_params("batch") == tv.default_params("batch")
+        assert tune.apply_cached("batch", "gfx950:batch:n2^10:nt2^25", path)
+        assert tv.get_params("batch") == params
+    finally:
+        tv.set_params("batch", None)
+    assert tune.size_class_single(5_557_093, (1024, 1024, 1024)) == "nt2^22:dims1024x1024x1024"
+    assert tune.size_class_batch(1024, 42_800_000) == "n2^10:nt2^25"
