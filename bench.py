@@ -21,6 +21,8 @@ Workloads (seeded synthetic Kuhn meshes, see paper_2106_01326_amd/synth.py):
           medium-shape meshes at 256^3) through the continuous-batching
           server at 0.5/0.7/0.9 x its measured capacity: p50/p99 latency and
           meshes/s
+  tune    the autotuner (paper_2106_01326_amd/tune.py) on the large, medium
+          and batch workloads: default vs tuned milliseconds and parameters
 """
 from __future__ import annotations
 
@@ -649,13 +651,69 @@ def cpu_baseline_batch(meshes, batch, target_s):
             "gpu_bit_exact_on_sample": exact}
 
 
+def tune_trials(r, defaults):
+    """Compact log of a tuner search: the fields each candidate changed from
+    the defaults, and its milliseconds."""
+    out = []
+    for e in r["log"]:
+        diff = {k: v for k, v in e["params"].items() if v != defaults[k]}
+        out.append([",".join(f"{k}={v}" for k, v in diff.items()) or "defaults", round(e["ms"], 4)])
+    return out
+
+
+def bench_tune(args, torch, tv):
+    """The autotuner on the large, medium and batch workloads.  Each search
+    starts from the library defaults and checks every candidate's grids
+    against the defaults' word for word; the line reports the large mesh's
+    tuned rate and, for each workload, default and tuned times."""
+    from paper_2106_01326_amd import synth, tune
+
+    dev = torch.device("cuda:0")
+    cache = os.path.join("gpurun_out", "tune_cache.json") if os.path.isdir("gpurun_out") else None
+    res = {}
+    for name in ("large", "medium"):
+        log(f"generating workload {name}")
+        m = make_workload(name)
+        q = m.verts is None
+        v = torch.from_numpy(m.qverts if q else m.verts).to(dev)
+        t = torch.from_numpy(m.tets).to(dev)
+        r = tune.tune_single(v, t, m.dims, None if q else m.bbox, qverts=q, reps=5, rounds=2, cache=cache)
+        res[name] = {"nt": m.nt, "ms_default": r["ms_default"], "ms_tuned": r["ms_best"],
+                     "speedup": r["ms_default"] / r["ms_best"], "params": r["params"], "key": r["key"],
+                     "trials": tune_trials(r, tv.default_params("single"))}
+        log(f"{name}: default {r['ms_default']:.4f} ms, tuned {r['ms_best']:.4f} ms with {r['params']}")
+        del v, t
+    log(f"generating {args.batch_meshes} batch meshes")
+    meshes = synth.workload_batch(count=args.batch_meshes)
+    items = [(torch.from_numpy(m.verts).to(dev), torch.from_numpy(m.tets).to(dev), m.dims, m.bbox, False)
+             for m in meshes]
+    r = tune.tune_batch(tv.Batch(items), reps=3, rounds=2, cache=cache)
+    res["batch"] = {"meshes": len(meshes), "ms_default": r["ms_default"], "ms_tuned": r["ms_best"],
+                    "speedup": r["ms_default"] / r["ms_best"], "params": r["params"], "key": r["key"],
+                    "trials": tune_trials(r, tv.default_params("batch"))}
+    log(f"batch: default {r['ms_default']:.4f} ms, tuned {r['ms_best']:.4f} ms with {r['params']}")
+    big = res["large"]
+    out = {"metric": "tets voxelized/s (autotuned launch parameters)", "value": big["nt"] / (big["ms_tuned"] * 1e-3),
+           "unit": "tets/s", "n_gpus": 1, "steps": 5, "warmup": 1, "ms_per_step": big["ms_tuned"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic (seeded jittered Kuhn meshes)",
+           "config": {"workload": "autotuner on the large (1024^3), medium (256^3) and batch workloads",
+                      "search": "coordinate search from the defaults, 2 rounds, median of 5 (3 for the batch) "
+                                "calls per candidate, every candidate bit-identical to the defaults"},
+           "tuned": res, "roofline": None,
+           "roofline_note": "the tuned calls run the same kernels as the large line, whose roofline applies",
+           "cpu_baseline": None}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="large",
-                    choices=["large", "medium", "small", "batch", "serving", "grids", "quality", "sweep"])
+                    choices=["large", "medium", "small", "batch", "serving", "grids", "quality", "sweep",
+                             "tune"])
     ap.add_argument("--requests", type=int, default=10000)
     ap.add_argument("--batch-meshes", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -696,6 +754,8 @@ def main():
         return bench_quality(args, torch, tv)
     if args.workload == "sweep":
         return bench_sweep(args, torch, tv)
+    if args.workload == "tune":
+        return bench_tune(args, torch, tv)
     log(f"generating workload {args.workload}")
     t0 = time.perf_counter()
     m = make_workload(args.workload)

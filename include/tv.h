@@ -198,12 +198,13 @@ tv_status tv_batch_run(const tv_batch_plan *plan, void *ws, size_t ws_bytes, voi
  *   tile_cols_log2  largest tile edge in columns, log2, in [3, 5]
  *   min_tiles       tiles are halved (down to 8 x 8 columns) while a grid
  *                   has fewer than this, in [1, 2^20]
- *   chunk_pieces    (tet, tile) pieces per work-queue task, in [64, 65536]
+ *   chunk_pieces    (tet, tile) pieces per work-queue task, in [64, 65536];
+ *                   0 picks about nt / 1024 (a power of two in [1024, 16384])
  *   strip_columns   kept columns per lane task, in [1, 64]
  *   piece_cap       tets meeting more tiles take the per-tet large path, [1, 8]
  *   wgs_per_cu      persistent tile workgroups per compute unit, in [1, 8]
- * Defaults (tv_default_params): single {5, 512, 4096, 8, 8, 2}, batch
- * {5, 1, 4096, 8, 8, 2}.  tv_set_params validates all fields
+ * Defaults (tv_default_params): single {5, 512, 0, 6, 8, 2}, batch
+ * {5, 1, 4096, 6, 8, 2}.  tv_set_params validates all fields
  * (TV_ERR_INVALID_ARG, nothing changed) and with p == NULL restores the
  * defaults.  The settings are process-wide; each call copies them when it
  * starts, so set them before enqueueing work.  Workspace sizes depend on

@@ -170,7 +170,7 @@ tv::MeshTable make_table(const tv::CallSizes &c, uint8_t *ws, const tv::MeshDesc
     tv::MeshTable T;
     memset(&T, 0, sizeof T);
     T.n = (int32_t)c.meshes;
-    T.chunk = P.chunk;
+    T.chunk = P.chunk ? P.chunk : tv::auto_chunk(c.nt);
     T.strip = P.strip;
     T.piece_cap = P.piece_cap;
     T.accumulate = (flags & TV_ACCUMULATE) ? 1 : 0;
@@ -430,8 +430,9 @@ tv_status tv_set_params(int32_t which, const tv_params *p) {
             return fail(TV_ERR_INVALID_ARG, "params: tile_cols_log2 %d not in [3,5]", p->tile_cols_log2);
         if (p->min_tiles < 1 || p->min_tiles > (1 << 20))
             return fail(TV_ERR_INVALID_ARG, "params: min_tiles %d not in [1,2^20]", p->min_tiles);
-        if (p->chunk_pieces < 64 || p->chunk_pieces > 65536)
-            return fail(TV_ERR_INVALID_ARG, "params: chunk_pieces %d not in [64,65536]", p->chunk_pieces);
+        if (p->chunk_pieces != 0 && (p->chunk_pieces < 64 || p->chunk_pieces > 65536))
+            return fail(TV_ERR_INVALID_ARG, "params: chunk_pieces %d neither 0 nor in [64,65536]",
+                        p->chunk_pieces);
         if (p->strip_columns < 1 || p->strip_columns > 64)
             return fail(TV_ERR_INVALID_ARG, "params: strip_columns %d not in [1,64]", p->strip_columns);
         if (p->piece_cap < 1 || p->piece_cap > tv::kPieceCap)

@@ -24,9 +24,20 @@ struct Params {
     int32_t wgs_per_cu;      // persistent tile workgroups per compute unit
 };
 // A lone grid wants >= 512 tiles to spread over the chip; batch meshes keep
-// the largest tiles (their parallelism comes from the mesh count).
-constexpr Params kDefaultSingle = {5, 512, 4096, 8, 8, 2};
-constexpr Params kDefaultBatch = {5, 1, 4096, 8, 8, 2};
+// the largest tiles (their parallelism comes from the mesh count).  chunk 0
+// sizes the queue tasks from the tet count (auto_chunk).  Values from the
+// autotuner's searches on the large, medium and batch workloads.
+constexpr Params kDefaultSingle = {5, 512, 0, 6, 8, 2};
+constexpr Params kDefaultBatch = {5, 1, 4096, 6, 8, 2};
+
+// Pieces per work-queue task when Params::chunk is 0: about nt / 1024
+// (a power of two in [1024, 16384]), so that a lone mesh of a few hundred
+// thousand tets is cut into enough tasks to keep every workgroup busy.
+inline int32_t auto_chunk(int64_t nt) {
+    int32_t c = 1024;
+    while (c < 16384 && (int64_t)c * 2 * 1024 <= nt) c *= 2;
+    return c;
+}
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 

@@ -15,6 +15,8 @@ SETTINGS = [
     {"strip_columns": 5},
     {"strip_columns": 64},
     {"chunk_pieces": 64},
+    {"chunk_pieces": 0},
+    {"chunk_pieces": 65536, "strip_columns": 8},
     {"piece_cap": 1},
     {"piece_cap": 3},
     {"tile_cols_log2": 3},
