@@ -201,10 +201,10 @@ __device__ __forceinline__ int32_t tet_pieces(const MeshDesc &d, const int4 *__r
 }
 
 // Both binning passes aggregate per workgroup: every piece's tile key goes
-// into an LDS hash table (open addressing, one slot per distinct key, an
-// LDS atomic gives the piece its rank among the workgroup's pieces of that
-// tile), then one global atomic per distinct key adds the workgroup's
-// count (pass 1) or reserves its slot range (pass 2).  Neighbouring tets,
+// into an LDS hash table (open addressing, one slot per distinct key; an
+// LDS atomic counts the piece, and in pass 2 gives it its rank among the
+// workgroup's pieces of that tile), then one global atomic per distinct key
+// adds the workgroup's count (pass 1) or reserves its slot range (pass 2).  Neighbouring tets,
 // which mostly share tiles, thus cost one global atomic per workgroup and
 // tile instead of one per piece.  A key that finds no free slot within
 // kHashProbes probes (a workgroup meeting very many tiles, e.g. shuffled
@@ -225,8 +225,14 @@ constexpr uint32_t kNoSlot = 0xffffffffu;
 __device__ __forceinline__ uint32_t hash_insert(uint32_t *keys, uint32_t key) {
     uint32_t h = (key * 2654435761u) >> (32 - 9);
     for (int i = 0; i < kHashProbes; ++i) {
-        const uint32_t prev = atomicCAS(keys + h, kEmptyKey, key);
-        if (prev == kEmptyKey || prev == key) return h;
+        // slots only go from empty to a key, so a plain read that finds the
+        // key (the common case: neighbouring tets share tiles) is final
+        const uint32_t cur = __hip_atomic_load(keys + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (cur == key) return h;
+        if (cur == kEmptyKey) {
+            const uint32_t prev = atomicCAS(keys + h, kEmptyKey, key);
+            if (prev == kEmptyKey || prev == key) return h;
+        }
         h = (h + 1) & (kHashSlots - 1);
     }
     return kNoSlot;
@@ -303,14 +309,17 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(MeshTable T, BinBuffers b) 
             const int32_t dy = rest % nys[u], dx = rest / nys[u];
             const uint32_t key = key0s[u] + (uint32_t)dx * sxs[u] + (uint32_t)dy * sys[u] + (uint32_t)dz;
             const uint32_t h = hash_insert(s_key, key);
-            uint32_t ref = kNoSlot;
-            if (h != kNoSlot) {
-                ref = (h << 16) | atomicAdd(s_cnt + h, 1u);
-            } else if (kScatter) {
-                b.pieces[b.tile_off[key] + atomicAdd(b.tile_cursor + key, 1u)] = (uint32_t)t;
-            } else {
-                atomicAdd(b.tile_count + key, 1u);
+            if (!kScatter) {
+                // counts only: the ranks are the scatter pass's business
+                if (h != kNoSlot) atomicAdd(s_cnt + h, 1u);
+                else atomicAdd(b.tile_count + key, 1u);
+                continue;
             }
+            uint32_t ref = kNoSlot;
+            if (h != kNoSlot)
+                ref = (h << 16) | atomicAdd(s_cnt + h, 1u);
+            else
+                b.pieces[b.tile_off[key] + atomicAdd(b.tile_cursor + key, 1u)] = (uint32_t)t;
             s_ref[(u * kBinThreads + tid) * kPieceCapMax + k] = ref;
         }
     }
