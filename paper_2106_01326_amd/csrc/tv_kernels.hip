@@ -342,59 +342,85 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(MeshTable T, BinBuffers b) 
     }
 }
 
-// Exclusive scan of the per-tile piece counts (one workgroup of 1024
-// threads, any tile count): tile_off[t] is the first piece slot of tile t;
-// chunk_off[t] the first chunk; meta[kMetaChunks] the chunk total.
+// Work-queue layout (one workgroup of 1024 threads, any tile count):
+//   tile_off[t]    first piece slot of tile t (exclusive scan in tile order);
+//   tile_order[r]  the tile of rank r: tiles sorted by size class
+//                  (floor(log2 pieces), larger first; empty tiles last);
+//   chunk_off[r]   first chunk of the tile of rank r (scan in rank order);
+//   meta[kMetaChunks] the chunk total.
+// Handing out the largest tasks first keeps the persistent workgroups busy
+// until the queue runs dry, instead of leaving a few large tiles for last.
+// The order inside a size class is whatever the atomics give; it changes
+// which workgroup does what, never the grid.
+__device__ __forceinline__ uint32_t tile_chunks(uint32_t pieces, uint32_t chunk) {
+    return pieces == 0 ? 1u : (pieces + chunk - 1) / chunk;
+}
+
+// Exclusive scan over the block of 1024 values (v at tid), continuing from
+// *carry; returns the exclusive prefix and advances *carry by the block
+// total.  s_w: 16 words of LDS.  Every thread must call it.
+__device__ __forceinline__ uint32_t scan1024(uint32_t v, uint32_t *carry, uint32_t *s_w, int tid) {
+    const int lane = tid & 63, wv = tid >> 6;
+    uint32_t inc = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t o = __shfl_up(inc, off);
+        if (lane >= off) inc += o;
+    }
+    if (lane == 63) s_w[wv] = inc;
+    __syncthreads();
+    uint32_t before = *carry;
+    for (int w = 0; w < wv; ++w) before += s_w[w];
+    uint32_t total = 0;
+    for (int w = 0; w < 16; ++w) total += s_w[w];
+    __syncthreads();  // s_w is rewritten by the next call
+    *carry += total;
+    return before + inc - v;
+}
+
 __global__ void __launch_bounds__(1024) k_scan_tiles(MeshTable T, BinBuffers b) {
-    __shared__ uint32_t s_wc[16], s_wk[16];  // per-wave totals, then their exclusive prefix
-    __shared__ uint32_t s_base_cnt, s_base_chk;
+    __shared__ uint32_t s_w[16];
+    __shared__ uint32_t s_class[33];  // tiles per size class, then each class's next rank
     const uint32_t nt = (uint32_t)T.ntiles_total;
     const uint32_t chunk = (uint32_t)T.chunk;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    uint32_t base_cnt = 0, base_chk = 0;  // totals of the tiles before this round
+    const int tid = threadIdx.x;
+    if (tid < 33) s_class[tid] = 0u;
+    __syncthreads();
+    // piece offsets in tile order; size-class histogram
+    uint32_t carry = 0;
     for (uint32_t base = 0; base < nt; base += 1024) {
         const uint32_t i = base + tid;
         const uint32_t c = i < nt ? b.tile_count[i] : 0u;
-        const uint32_t k = i < nt ? (c == 0 ? 1u : (c + chunk - 1) / chunk) : 0u;
-        // inclusive scans within the wave
-        uint32_t ic = c, ik = k;
-        for (int off = 1; off < 64; off <<= 1) {
-            const uint32_t oc = __shfl_up(ic, off), ok = __shfl_up(ik, off);
-            if (lane >= off) {
-                ic += oc;
-                ik += ok;
-            }
-        }
-        if (lane == 63) {
-            s_wc[wv] = ic;
-            s_wk[wv] = ik;
-        }
-        __syncthreads();
-        if (tid == 0) {
-            uint32_t ac = base_cnt, ak = base_chk;
-            for (int w = 0; w < 16; ++w) {
-                const uint32_t tc = s_wc[w], tk = s_wk[w];
-                s_wc[w] = ac;
-                s_wk[w] = ak;
-                ac += tc;
-                ak += tk;
-            }
-            s_base_cnt = ac;
-            s_base_chk = ak;
-        }
-        __syncthreads();
+        const uint32_t off = scan1024(c, &carry, s_w, tid);
         if (i < nt) {
-            b.tile_off[i] = s_wc[wv] + ic - c;
-            b.chunk_off[i] = s_wk[wv] + ik - k;
+            b.tile_off[i] = off;
+            atomicAdd(&s_class[__clz(c)], 1u);  // class 32: empty tiles
         }
-        base_cnt = s_base_cnt;
-        base_chk = s_base_chk;
-        __syncthreads();  // s_wc / s_wk are rewritten next round
     }
     if (tid == 0) {
-        b.tile_off[nt] = base_cnt;
-        b.chunk_off[nt] = base_chk;
-        b.meta[kMetaChunks] = base_chk;
+        b.tile_off[nt] = carry;
+        uint32_t acc = 0;
+        for (int k = 0; k < 33; ++k) {
+            const uint32_t n = s_class[k];
+            s_class[k] = acc;
+            acc += n;
+        }
+    }
+    __syncthreads();
+    // ranks: tiles of larger classes first
+    for (uint32_t i = tid; i < nt; i += 1024)
+        b.tile_order[atomicAdd(&s_class[__clz(b.tile_count[i])], 1u)] = i;
+    __syncthreads();  // tile_order is read back by other threads below
+    // chunk offsets in rank order
+    carry = 0;
+    for (uint32_t base = 0; base < nt; base += 1024) {
+        const uint32_t r = base + tid;
+        const uint32_t k = r < nt ? tile_chunks(b.tile_count[b.tile_order[r]], chunk) : 0u;
+        const uint32_t off = scan1024(k, &carry, s_w, tid);
+        if (r < nt) b.chunk_off[r] = off;
+    }
+    if (tid == 0) {
+        b.chunk_off[nt] = carry;
+        b.meta[kMetaChunks] = carry;
     }
 }
 
@@ -414,7 +440,7 @@ __device__ __forceinline__ TileOrigin tile_origin(uint32_t lt, const TilePlan &p
 __global__ void k_zero_shared_tiles(MeshTable T, BinBuffers b) {
     const uint32_t tile = blockIdx.x;
     if (tile >= (uint32_t)T.ntiles_total) return;
-    if (b.chunk_off[tile + 1] - b.chunk_off[tile] <= 1) return;
+    if (b.tile_count[tile] <= (uint32_t)T.chunk) return;  // one chunk: plain stores
     const int32_t m = T.n == 1 ? 0 : find_mesh(T.tile_pre, T.n, (int64_t)tile);
     const MeshDesc &d = mesh_desc(T, m);
     const TileOrigin o = tile_origin(tile - (uint32_t)d.tile_base, d.p);
@@ -590,7 +616,7 @@ __global__ void __launch_bounds__(kTileThreads)
             const uint32_t c = atomicAdd(&b.meta[kMetaQueue], 1u);
             s_chunk = c;
             if (c < total) {
-                // tile = last t with chunk_off[t] <= c
+                // rank = last r with chunk_off[r] <= c
                 uint32_t lo = 0, hi = (uint32_t)T.ntiles_total;  // chunk_off[lo] <= c < chunk_off[hi]
                 while (hi - lo > 1) {
                     const uint32_t mid = (lo + hi) >> 1;
@@ -599,12 +625,13 @@ __global__ void __launch_bounds__(kTileThreads)
                 }
                 const uint32_t k = c - b.chunk_off[lo];
                 const uint32_t nchunks = b.chunk_off[lo + 1] - b.chunk_off[lo];
-                const uint32_t pb = b.tile_off[lo], pe = b.tile_off[lo + 1];
-                s_tile = lo;
+                const uint32_t tile = b.tile_order[lo];
+                const uint32_t pb = b.tile_off[tile], pe = b.tile_off[tile + 1];
+                s_tile = tile;
                 s_p0 = min(pe, pb + k * (uint32_t)T.chunk);
                 s_p1 = min(pe, pb + (k + 1) * (uint32_t)T.chunk);
                 s_shared = nchunks > 1 ? 1u : 0u;
-                s_mesh = T.n == 1 ? 0 : find_mesh(T.tile_pre, T.n, (int64_t)lo);
+                s_mesh = T.n == 1 ? 0 : find_mesh(T.tile_pre, T.n, (int64_t)tile);
             }
         }
         __syncthreads();

@@ -88,6 +88,7 @@ struct WorkspaceLayout {
     size_t clear_end;    // [0, clear_end) is zeroed at the start of a call
     size_t tile_off;     // ntiles + 1
     size_t chunk_off;    // ntiles + 1
+    size_t tile_order;   // ntiles
     size_t descs;        // meshes MeshDesc, then 3 x (meshes + 1) int64 prefix sums
     size_t descs_bytes;
     size_t q4;           // nv int4 lattice vertices (.w = invalid flag)
@@ -118,6 +119,8 @@ inline WorkspaceLayout layout(const CallSizes &c) {
     off = align256(off + 4 * ((size_t)c.ntiles + 1));
     L.chunk_off = off;
     off = align256(off + 4 * ((size_t)c.ntiles + 1));
+    L.tile_order = off;
+    off = align256(off + 4 * (size_t)c.ntiles);
     L.descs = off;
     L.descs_bytes = c.table ? sizeof(MeshDesc) * (size_t)c.meshes +
                                   3 * sizeof(int64_t) * ((size_t)c.meshes + 1)
@@ -143,6 +146,7 @@ inline BinBuffers bin_buffers(uint8_t *ws, const WorkspaceLayout &L) {
     b.tile_cursor = reinterpret_cast<uint32_t *>(ws + L.tile_cursor);
     b.tile_off = reinterpret_cast<uint32_t *>(ws + L.tile_off);
     b.chunk_off = reinterpret_cast<uint32_t *>(ws + L.chunk_off);
+    b.tile_order = reinterpret_cast<uint32_t *>(ws + L.tile_order);
     b.pieces = reinterpret_cast<uint32_t *>(ws + L.pieces);
     b.big = reinterpret_cast<uint32_t *>(ws + L.big);
     b.trec = reinterpret_cast<uint2 *>(ws + L.trec);
