@@ -31,10 +31,10 @@ constexpr Params kDefaultSingle = {5, 512, 0, 6, 8, 2};
 constexpr Params kDefaultBatch = {5, 1, 4096, 6, 8, 2};
 
 // Pieces per work-queue task when Params::chunk is 0: about nt / 1024
-// (a power of two in [1024, 16384]), so that a lone mesh of a few hundred
+// (a power of two in [256, 16384]), so that a lone mesh of a few hundred
 // thousand tets is cut into enough tasks to keep every workgroup busy.
 inline int32_t auto_chunk(int64_t nt) {
-    int32_t c = 1024;
+    int32_t c = 256;
     while (c < 16384 && (int64_t)c * 2 * 1024 <= nt) c *= 2;
     return c;
 }

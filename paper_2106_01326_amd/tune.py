@@ -27,7 +27,7 @@ import paper_2106_01326_amd as tv
 # values tried per field (the default is always among them)
 CANDIDATES = {
     "strip_columns": (4, 6, 8, 12, 16),
-    "chunk_pieces": (0, 1024, 2048, 4096, 8192, 16384),
+    "chunk_pieces": (0, 256, 512, 1024, 2048, 4096, 8192, 16384),
     "tile_cols_log2": (5, 4),
     "min_tiles": (256, 512, 1024, 2048),
     "piece_cap": (2, 4, 8),
