@@ -199,7 +199,8 @@ tv_status tv_batch_run(const tv_batch_plan *plan, void *ws, size_t ws_bytes, voi
  *   min_tiles       tiles are halved (down to 8 x 8 columns) while a grid
  *                   has fewer than this, in [1, 2^20]
  *   chunk_pieces    (tet, tile) pieces per work-queue task, in [64, 65536];
- *                   0 picks about nt / 1024 (a power of two in [256, 16384])
+ *                   0 picks about nt / 2048 (a power of two in [256, 16384];
+ *                   at least 4096 when the call has 4096 tiles or more)
  *   strip_columns   kept columns per lane task, in [1, 64]
  *   piece_cap       tets meeting more tiles take the per-tet large path, [1, 8]
  *   wgs_per_cu      persistent tile workgroups per compute unit, in [1, 8]

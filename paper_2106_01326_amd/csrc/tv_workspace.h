@@ -30,12 +30,15 @@ struct Params {
 constexpr Params kDefaultSingle = {5, 512, 0, 6, 8, 2};
 constexpr Params kDefaultBatch = {5, 1, 4096, 6, 8, 2};
 
-// Pieces per work-queue task when Params::chunk is 0: about nt / 1024
-// (a power of two in [256, 16384]), so that a lone mesh of a few hundred
-// thousand tets is cut into enough tasks to keep every workgroup busy.
-inline int32_t auto_chunk(int64_t nt) {
+// Pieces per work-queue task when Params::chunk is 0: about 4096 tasks in
+// all (pieces, about 2 per tet, / 4096 = nt / 2048), a power of two in
+// [256, 16384].  A call that already has 4096 tiles or more keeps at least
+// 4096 pieces per task: more tasks would only split its tiles into shares
+// that are flushed with atomics.
+inline int32_t auto_chunk(int64_t nt, int64_t ntiles) {
     int32_t c = 256;
-    while (c < 16384 && (int64_t)c * 2 * 1024 <= nt) c *= 2;
+    while (c < 16384 && (int64_t)c * 2 * 2048 <= nt) c *= 2;
+    if (ntiles >= 4096 && c < 4096) c = 4096;
     return c;
 }
 
