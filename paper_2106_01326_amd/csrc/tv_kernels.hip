@@ -42,17 +42,21 @@ __device__ __forceinline__ const MeshDesc &mesh_desc(const MeshTable &T, int32_t
     return T.descs ? T.descs[m] : T.one;
 }
 
-// Mesh of global index x for the threads of one workgroup whose indices are
-// [first, last]: two threads bracket the workgroup's meshes once, then each
-// thread searches only inside the bracket (usually a single mesh).  Must be
-// called by every thread of the workgroup.
-__device__ __forceinline__ int32_t find_mesh_block(const MeshTable &T, const int64_t *pre,
-                                                   int64_t first, int64_t last, int64_t x,
-                                                   int32_t *s_bracket) {
-    if (T.n == 1) return 0;
+// Meshes of the global indices [first, last] of one workgroup: threads 0 and
+// 1 search the bounds once (every thread must call this), then
+// mesh_in_bracket finds each index's mesh inside the bracket (usually a
+// single mesh, so no search at all).
+__device__ __forceinline__ void mesh_bracket(const MeshTable &T, const int64_t *pre, int64_t first,
+                                             int64_t last, int32_t *s_bracket) {
+    if (T.n == 1) return;
     if (threadIdx.x == 0) s_bracket[0] = find_mesh(pre, T.n, first);
     if (threadIdx.x == 1) s_bracket[1] = find_mesh(pre, T.n, last);
     __syncthreads();
+}
+
+__device__ __forceinline__ int32_t mesh_in_bracket(const MeshTable &T, const int64_t *pre, int64_t x,
+                                                   const int32_t *s_bracket) {
+    if (T.n == 1) return 0;
     int32_t lo = s_bracket[0], hi = s_bracket[1] + 1;  // pre[lo] <= x < pre[hi]
     while (hi - lo > 1) {
         const int32_t mid = (lo + hi) >> 1;
@@ -87,7 +91,8 @@ __global__ void k_ingest(MeshTable T, BinBuffers b) {
     const int64_t first = (int64_t)blockIdx.x * blockDim.x;
     const int64_t last = min(first + (int64_t)blockDim.x, T.nv_total) - 1;
     const int64_t v = first + threadIdx.x;
-    const int32_t m = find_mesh_block(T, T.vert_pre, first, last, min(v, last), s_bracket);
+    mesh_bracket(T, T.vert_pre, first, last, s_bracket);
+    const int32_t m = mesh_in_bracket(T, T.vert_pre, min(v, last), s_bracket);
     if (v >= T.nv_total) return;
     const MeshDesc &d = mesh_desc(T, m);
     const int64_t i = v - d.vert_base;
@@ -213,7 +218,9 @@ __device__ __forceinline__ int32_t tet_pieces(const MeshDesc &d, const int4 *__r
 // key and the tile range's shape), so the scatter pass reads 8 bytes per tet
 // instead of gathering and boxing the tet again.
 constexpr int kBinThreads = 256;
-constexpr int kBinTets = 2;  // tets per thread
+// tets per thread: 4 once a call has enough tets to fill the chip with
+// 1024-tet workgroups (kBinTetsMany), else 2
+constexpr int64_t kBinTetsMany = (int64_t)1 << 21;
 constexpr int kHashSlots = 512;
 constexpr int kHashProbes = 32;
 constexpr int kPieceCapMax = 8;
@@ -247,7 +254,7 @@ __device__ __forceinline__ uint2 encode_trec(uint32_t key0, const TileRange &r, 
                                 (uint32_t)(r.z1 - r.z0) << 7);
 }
 
-template <bool kScatter>
+template <bool kScatter, int kBinTets>
 __global__ void __launch_bounds__(kBinThreads) k_bin(MeshTable T, BinBuffers b) {
     __shared__ uint32_t s_key[kHashSlots];
     __shared__ uint32_t s_cnt[kHashSlots];  // count, then (pass 2) global slot base
@@ -265,10 +272,11 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(MeshTable T, BinBuffers b) 
     const int64_t last = min(first + (int64_t)(kBinThreads * kBinTets), T.nt_total) - 1;
     int32_t np[kBinTets], nys[kBinTets], nzs[kBinTets];
     uint32_t key0s[kBinTets], sys[kBinTets], sxs[kBinTets];
+    mesh_bracket(T, T.tet_pre, first, last, s_bracket);
 #pragma unroll
     for (int u = 0; u < kBinTets; ++u) {
         const int64_t t = first + u * kBinThreads + tid;
-        const int32_t m = find_mesh_block(T, T.tet_pre, first, last, min(t, last), s_bracket);
+        const int32_t m = mesh_in_bracket(T, T.tet_pre, min(t, last), s_bracket);
         np[u] = 0;
         nys[u] = nzs[u] = 1;
         key0s[u] = sys[u] = sxs[u] = 0;
@@ -406,15 +414,20 @@ __global__ void __launch_bounds__(1024) k_scan_tiles(MeshTable T, BinBuffers b) 
         }
     }
     __syncthreads();
-    // ranks: tiles of larger classes first
-    for (uint32_t i = tid; i < nt; i += 1024)
-        b.tile_order[atomicAdd(&s_class[__clz(b.tile_count[i])], 1u)] = i;
-    __syncthreads();  // tile_order is read back by other threads below
+    // ranks: tiles of larger classes first; chunk_off[r] holds the rank's
+    // chunk count until the scan below turns it into an offset
+    for (uint32_t i = tid; i < nt; i += 1024) {
+        const uint32_t c = b.tile_count[i];
+        const uint32_t r = atomicAdd(&s_class[__clz(c)], 1u);
+        b.tile_order[r] = i;
+        b.chunk_off[r] = tile_chunks(c, chunk);
+    }
+    __syncthreads();  // chunk_off is read back by other threads below
     // chunk offsets in rank order
     carry = 0;
     for (uint32_t base = 0; base < nt; base += 1024) {
         const uint32_t r = base + tid;
-        const uint32_t k = r < nt ? tile_chunks(b.tile_count[b.tile_order[r]], chunk) : 0u;
+        const uint32_t k = r < nt ? b.chunk_off[r] : 0u;
         const uint32_t off = scan1024(k, &carry, s_w, tid);
         if (r < nt) b.chunk_off[r] = off;
     }
@@ -981,8 +994,10 @@ void launch_set_word(uint32_t *p, uint32_t value, hipStream_t s) {
 }
 
 void launch_bin_count(const MeshTable &T, const BinBuffers &b, hipStream_t s) {
-    if (T.nt_total > 0)
-        k_bin<false><<<blocks_for(T.nt_total, kBinThreads * kBinTets), kBinThreads, 0, s>>>(T, b);
+    if (T.nt_total >= kBinTetsMany)
+        k_bin<false, 4><<<blocks_for(T.nt_total, kBinThreads * 4), kBinThreads, 0, s>>>(T, b);
+    else if (T.nt_total > 0)
+        k_bin<false, 2><<<blocks_for(T.nt_total, kBinThreads * 2), kBinThreads, 0, s>>>(T, b);
 }
 
 void launch_scan_tiles(const MeshTable &T, const BinBuffers &b, hipStream_t s) {
@@ -990,8 +1005,10 @@ void launch_scan_tiles(const MeshTable &T, const BinBuffers &b, hipStream_t s) {
 }
 
 void launch_bin_scatter(const MeshTable &T, const BinBuffers &b, hipStream_t s) {
-    if (T.nt_total > 0)
-        k_bin<true><<<blocks_for(T.nt_total, kBinThreads * kBinTets), kBinThreads, 0, s>>>(T, b);
+    if (T.nt_total >= kBinTetsMany)
+        k_bin<true, 4><<<blocks_for(T.nt_total, kBinThreads * 4), kBinThreads, 0, s>>>(T, b);
+    else if (T.nt_total > 0)
+        k_bin<true, 2><<<blocks_for(T.nt_total, kBinThreads * 2), kBinThreads, 0, s>>>(T, b);
 }
 
 void launch_zero_shared_tiles(const MeshTable &T, const BinBuffers &b, hipStream_t s) {

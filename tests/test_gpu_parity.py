@@ -299,6 +299,17 @@ def test_medium_workload_full_grid(oracle_mod, medium, per_tet):
     assert_same(got, oracle_words(oracle_mod, medium), "medium")
 
 
+def test_many_tets_full_grid(oracle_mod):
+    """A mesh above the binning's many-tets threshold (2^21 tets: four tets
+    per binning thread) against the oracle over the whole 256^3 grid."""
+    m = synth.make_mesh(72, 0.3, 256, "all", 0, 3301)
+    assert m.nt >= 1 << 21
+    banner(f"many-tets mesh nt={m.nt}")
+    got, st = gpu_voxelize_mesh(m)
+    assert st == 0
+    assert_same(got, oracle_words(oracle_mod, m), "many tets")
+
+
 def test_large_workload_sampled_windows(oracle_mod, large):
     """1024^3 grid: the oracle recomputes random windows one by one (every
     tet, only the window's voxels), compared bit for bit."""
