@@ -103,3 +103,26 @@ def test_autotuner_runs_and_caches(cases, tmp_path):
     assert rb["ms_best"] <= rb["ms_default"]
     assert tune.cached(rb["key"], cache)["params"] == rb["params"]
     assert tv.get_params("batch") == tv.default_params("batch")
+
+
+def test_batch_with_many_tiles(oracle_mod):
+    """Many tiles in one call (the queue-layout scan runs 19 rounds of 1024
+    tiles): 300 meshes on 64^3 grids cut into 8x8-column tiles."""
+    import torch
+
+    import paper_2106_01326_amd as tv
+
+    ms = [synth.make_mesh(4 + (i % 5), 0.3, 64, "ellipsoids", 1 + i % 3, 9300 + i) for i in range(300)]
+    banner(f"batch of {len(ms)} meshes with 8x8-column tiles")
+    try:
+        tv.set_params("batch", tile_cols_log2=3, min_tiles=1 << 20)
+        items = [(torch.from_numpy(m.verts).cuda(), torch.from_numpy(m.tets).cuda(), m.dims, m.bbox, False)
+                 for m in ms]
+        b = tv.Batch(items)
+        plan = b.prepare()
+        assert plan.ntiles > 16384
+        for i, g in enumerate(b.run_prepared()):
+            assert np.array_equal(to_numpy_words(g), oracle_mod.voxelize_mesh(ms[i])), f"mesh {i}"
+            assert b.status(i) == tv.TV_OK
+    finally:
+        tv.set_params("batch", None)
