@@ -84,7 +84,9 @@ typedef int32_t tv_status;
                                cleared grid (same output, slower; for A/B checks) */
 #define TV_ACCUMULATE 8u    /* OR the voxels into the grid instead of overwriting it (the
                                grid must hold a previous result or zeros), and keep the
-                               data-error status words of earlier calls on this workspace:
+                               data-error status words of earlier calls on this workspace
+                               (so a fresh workspace's first call must not accumulate,
+                               or come from tv_batch_prepare, which clears them):
                                voxelizing a mesh in several tet subsets gives its grid */
 
 typedef struct {
@@ -159,9 +161,12 @@ tv_status tv_voxelize_batch(const tv_mesh *meshes, int32_t n, void *ws, size_t w
  * against it); only the descriptor upload is split off.
  *
  * tv_batch_prepare checks the meshes as tv_voxelize_batch does, copies their
- * descriptor table into `ws` (asynchronously on `stream`, from pageable
- * host memory, so `meshes` may be reused when it returns) and fills *plan, a
- * small host struct owned by the caller.  It enqueues no kernel.
+ * descriptor table into `ws` and clears the meshes' status words
+ * (asynchronously on `stream`: a copy from pageable host memory, so `meshes`
+ * may be reused when it returns, and a memset; no kernel), and fills *plan,
+ * a small host struct owned by the caller.  Runs of a plan prepared with
+ * TV_ACCUMULATE therefore report the data errors of every run since the
+ * prepare.
  * TV_PATH_PER_TET is rejected (TV_ERR_INVALID_ARG).
  *
  * tv_batch_run enqueues the batch's kernels on `stream` and nothing else: no

@@ -463,6 +463,11 @@ tv_status tv_batch_prepare(const tv_mesh *meshes, int32_t n, void *ws, size_t ws
     if ((st = check_ws(ws, ws_bytes, tv::layout(c).total, flags))) return st;
     if ((st = upload_table(descs, c, static_cast<uint8_t *>(ws), reinterpret_cast<hipStream_t>(stream))))
         return st;
+    // runs with TV_ACCUMULATE keep the status words: start them clear
+    const tv::WorkspaceLayout L = tv::layout(c);
+    if (hipMemsetAsync(static_cast<uint8_t *>(ws) + L.status, 0, 4 * (size_t)tv::status_words(c.meshes),
+                       reinterpret_cast<hipStream_t>(stream)) != hipSuccess)
+        return fail(TV_ERR_HIP, "status clear failed");
     plan->meshes = c.meshes;
     plan->nv = c.nv;
     plan->nt = c.nt;

@@ -187,3 +187,35 @@ def test_prepared_batch_runs(oracle_mod, uneven):
     lib = tv.load_library()
     st = lib.tv_batch_run(ctypes.byref(b.plan), ctypes.c_void_p(other.data_ptr()), other.numel(), None)
     assert st == tv.TV_ERR_INVALID_ARG and b"another workspace" in lib.tv_last_error()
+
+
+def test_prepared_batch_accumulates(oracle_mod):
+    """A batch prepared with TV_ACCUMULATE ORs each run into the grids: two
+    runs over the two halves of every mesh's tets (swapped in place between
+    the runs) give the whole mesh's grid."""
+    import torch
+
+    import paper_2106_01326_amd as tv
+
+    ms = synth.workload_batch(first=8, workers=1)
+    banner(f"accumulating prepared batch of {len(ms)} meshes")
+    halves = []
+    items = []
+    for m in ms:
+        h = m.nt // 2
+        a, b = np.ascontiguousarray(m.tets[:h]), np.ascontiguousarray(m.tets[h:2 * h])
+        halves.append((a, b))
+        items.append((torch.from_numpy(m.verts).cuda(), torch.from_numpy(a).cuda(), m.dims, m.bbox, False))
+    b = tv.Batch(items)
+    for g in b.grids:
+        g.zero_()
+    b.prepare(accumulate=True)
+    b.run_prepared()
+    for (a, bb), it in zip(halves, items):
+        it[1].copy_(torch.from_numpy(bb).cuda())
+    grids = b.run_prepared()
+    for i, m in enumerate(ms):
+        h = m.nt // 2
+        even = synth.Mesh(tets=m.tets[:2 * h], dims=m.dims, bbox=m.bbox, verts=m.verts)
+        assert np.array_equal(to_numpy_words(grids[i]), oracle_mod.voxelize_mesh(even)), f"mesh {i}"
+        assert b.status(i) == tv.TV_OK
