@@ -327,6 +327,8 @@ def voxelize(verts, tets, dims, bbox=None, *, qverts=False, strict=False, per_te
     need = workspace_bytes(nv, nt, dims, flags)
     if workspace is None:
         workspace = alloc_workspace(need, verts.device)
+        if accumulate:
+            workspace.zero_()  # an accumulating call keeps the status words it finds
     wptr, _ = _dev_ptr(workspace, torch.uint8, None, "workspace")
     s = _stream_handle(stream)
     if qverts:
