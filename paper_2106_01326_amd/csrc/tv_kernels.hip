@@ -254,7 +254,7 @@ __device__ __forceinline__ uint2 encode_trec(uint32_t key0, const TileRange &r, 
                                 (uint32_t)(r.z1 - r.z0) << 7);
 }
 
-template <bool kScatter, int kBinTets>
+template <bool kScatter, int kBinTets, bool kTable>
 __global__ void __launch_bounds__(kBinThreads) k_bin(MeshTable T, BinBuffers b) {
     __shared__ uint32_t s_key[kHashSlots];
     __shared__ uint32_t s_cnt[kHashSlots];  // count, then (pass 2) global slot base
@@ -273,39 +273,54 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(MeshTable T, BinBuffers b) 
     int32_t np[kBinTets], nys[kBinTets], nzs[kBinTets];
     uint32_t key0s[kBinTets], sys[kBinTets], sxs[kBinTets];
     mesh_bracket(T, T.tet_pre, first, last, s_bracket);
+    // the tile summary of this thread's tet slot u (tet t of mesh d)
+    auto tile_summary = [&](int u, int64_t t, const MeshDesc &d) {
+        sys[u] = (uint32_t)d.p.ntz;
+        sxs[u] = (uint32_t)d.p.nty * sys[u];
+        if (!kScatter) {
+            TileRange r = {0, -1, 0, -1, 0, -1};
+            int32_t n = tet_pieces(d, b.q4, t - d.tet_base, b.status, r);
+            if (n > T.piece_cap) {
+                b.big[atomicAdd(&b.meta[kMetaBig], 1u)] = (uint32_t)t;
+                n = 0;
+            }
+            key0s[u] = (uint32_t)d.tile_base + tile_id(r.x0, r.y0, r.z0, d.p);
+            b.trec[t] = encode_trec(key0s[u], r, n);
+            np[u] = n;
+            nys[u] = r.y1 - r.y0 + 1;
+            nzs[u] = r.z1 - r.z0 + 1;
+        } else {
+            const uint2 rec = b.trec[t];
+            if (rec.y) {
+                key0s[u] = rec.x;
+                const int32_t nx = (int32_t)((rec.y >> 1) & 7u) + 1;
+                nys[u] = (int32_t)((rec.y >> 4) & 7u) + 1;
+                nzs[u] = (int32_t)((rec.y >> 7) & 7u) + 1;
+                np[u] = nx * nys[u] * nzs[u];
+            }
+        }
+    };
 #pragma unroll
     for (int u = 0; u < kBinTets; ++u) {
-        const int64_t t = first + u * kBinThreads + tid;
-        const int32_t m = mesh_in_bracket(T, T.tet_pre, min(t, last), s_bracket);
         np[u] = 0;
         nys[u] = nzs[u] = 1;
         key0s[u] = sys[u] = sxs[u] = 0;
-        if (t < T.nt_total) {
-            const MeshDesc &d = mesh_desc(T, m);
-            sys[u] = (uint32_t)d.p.ntz;
-            sxs[u] = (uint32_t)d.p.nty * sys[u];
-            if (!kScatter) {
-                TileRange r = {0, -1, 0, -1, 0, -1};
-                int32_t n = tet_pieces(d, b.q4, t - d.tet_base, b.status, r);
-                if (n > T.piece_cap) {
-                    b.big[atomicAdd(&b.meta[kMetaBig], 1u)] = (uint32_t)t;
-                    n = 0;
-                }
-                key0s[u] = (uint32_t)d.tile_base + tile_id(r.x0, r.y0, r.z0, d.p);
-                b.trec[t] = encode_trec(key0s[u], r, n);
-                np[u] = n;
-                nys[u] = r.y1 - r.y0 + 1;
-                nzs[u] = r.z1 - r.z0 + 1;
-            } else {
-                const uint2 rec = b.trec[t];
-                if (rec.y) {
-                    key0s[u] = rec.x;
-                    const int32_t nx = (int32_t)((rec.y >> 1) & 7u) + 1;
-                    nys[u] = (int32_t)((rec.y >> 4) & 7u) + 1;
-                    nzs[u] = (int32_t)((rec.y >> 7) & 7u) + 1;
-                    np[u] = nx * nys[u] * nzs[u];
-                }
-            }
+    }
+    if (kTable && (T.n == 1 || s_bracket[0] == s_bracket[1])) {
+        // a table call whose workgroup lies in one mesh reads the descriptor
+        // once, not once per tet
+        const MeshDesc d = T.descs[T.n == 1 ? 0 : s_bracket[0]];
+#pragma unroll
+        for (int u = 0; u < kBinTets; ++u) {
+            const int64_t t = first + u * kBinThreads + tid;
+            if (t < T.nt_total) tile_summary(u, t, d);
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < kBinTets; ++u) {
+            const int64_t t = first + u * kBinThreads + tid;
+            if (t < T.nt_total)
+                tile_summary(u, t, mesh_desc(T, mesh_in_bracket(T, T.tet_pre, min(t, last), s_bracket)));
         }
     }
     __syncthreads();  // the table is clear
@@ -993,11 +1008,24 @@ void launch_set_word(uint32_t *p, uint32_t value, hipStream_t s) {
     k_set_word<<<1, 1, 0, s>>>(p, value);
 }
 
+// One binning pass, instantiated for the tets per thread and for a call
+// with a descriptor table (batches) or a single descriptor argument.
+template <bool kScatter>
+void launch_bin(const MeshTable &T, const BinBuffers &b, hipStream_t s) {
+    if (T.nt_total <= 0) return;
+    const bool many = T.nt_total >= kBinTetsMany;
+    const unsigned blocks = (unsigned)blocks_for(T.nt_total, kBinThreads * (many ? 4 : 2));
+    if (T.descs) {
+        if (many) k_bin<kScatter, 4, true><<<blocks, kBinThreads, 0, s>>>(T, b);
+        else k_bin<kScatter, 2, true><<<blocks, kBinThreads, 0, s>>>(T, b);
+    } else {
+        if (many) k_bin<kScatter, 4, false><<<blocks, kBinThreads, 0, s>>>(T, b);
+        else k_bin<kScatter, 2, false><<<blocks, kBinThreads, 0, s>>>(T, b);
+    }
+}
+
 void launch_bin_count(const MeshTable &T, const BinBuffers &b, hipStream_t s) {
-    if (T.nt_total >= kBinTetsMany)
-        k_bin<false, 4><<<blocks_for(T.nt_total, kBinThreads * 4), kBinThreads, 0, s>>>(T, b);
-    else if (T.nt_total > 0)
-        k_bin<false, 2><<<blocks_for(T.nt_total, kBinThreads * 2), kBinThreads, 0, s>>>(T, b);
+    launch_bin<false>(T, b, s);
 }
 
 void launch_scan_tiles(const MeshTable &T, const BinBuffers &b, hipStream_t s) {
@@ -1005,10 +1033,7 @@ void launch_scan_tiles(const MeshTable &T, const BinBuffers &b, hipStream_t s) {
 }
 
 void launch_bin_scatter(const MeshTable &T, const BinBuffers &b, hipStream_t s) {
-    if (T.nt_total >= kBinTetsMany)
-        k_bin<true, 4><<<blocks_for(T.nt_total, kBinThreads * 4), kBinThreads, 0, s>>>(T, b);
-    else if (T.nt_total > 0)
-        k_bin<true, 2><<<blocks_for(T.nt_total, kBinThreads * 2), kBinThreads, 0, s>>>(T, b);
+    launch_bin<true>(T, b, s);
 }
 
 void launch_zero_shared_tiles(const MeshTable &T, const BinBuffers &b, hipStream_t s) {
