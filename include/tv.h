@@ -185,7 +185,7 @@ typedef struct {
     int64_t meshes, nv, nt, ntiles; /* totals of the prepared batch */
     uint64_t ws;                    /* address of the workspace holding the table */
     uint32_t flags;                 /* flags given to tv_batch_prepare */
-    int32_t launch[4];              /* launch parameters in force at prepare time */
+    int32_t launch[5];              /* launch parameters in force at prepare time */
     uint32_t check;                 /* consistency tag */
 } tv_batch_plan;
 
@@ -209,8 +209,10 @@ tv_status tv_batch_run(const tv_batch_plan *plan, void *ws, size_t ws_bytes, voi
  *   strip_columns   kept columns per lane task, in [1, 64]
  *   piece_cap       tets meeting more tiles take the per-tet large path, [1, 8]
  *   wgs_per_cu      persistent tile workgroups per compute unit, in [1, 8]
- * Defaults (tv_default_params): single {5, 512, 0, 6, 8, 2}, batch
- * {5, 1, 4096, 6, 8, 2}.  tv_set_params validates all fields
+ *   cull_columns    a piece whose clipped box has at most this many columns
+ *                   skips the per-row culling by its xy hull, in [0, 1024]
+ * Defaults (tv_default_params): single {5, 512, 0, 6, 8, 2, 3}, batch
+ * {5, 1, 4096, 6, 8, 2, 6}.  tv_set_params validates all fields
  * (TV_ERR_INVALID_ARG, nothing changed) and with p == NULL restores the
  * defaults.  The settings are process-wide; each call copies them when it
  * starts, so set them before enqueueing work.  Workspace sizes depend on
@@ -220,7 +222,8 @@ tv_status tv_batch_run(const tv_batch_plan *plan, void *ws, size_t ws_bytes, voi
  * the Python package (timings on the device, a JSON cache).
  */
 typedef struct {
-    int32_t tile_cols_log2, min_tiles, chunk_pieces, strip_columns, piece_cap, wgs_per_cu;
+    int32_t tile_cols_log2, min_tiles, chunk_pieces, strip_columns, piece_cap, wgs_per_cu,
+        cull_columns;
 } tv_params;
 #define TV_PARAMS_SINGLE 0
 #define TV_PARAMS_BATCH 1

@@ -78,10 +78,11 @@ class MeshC(ctypes.Structure):
 class BatchPlanC(ctypes.Structure):
     _fields_ = [("meshes", ctypes.c_int64), ("nv", ctypes.c_int64), ("nt", ctypes.c_int64),
                 ("ntiles", ctypes.c_int64), ("ws", ctypes.c_uint64), ("flags", ctypes.c_uint32),
-                ("launch", ctypes.c_int32 * 4), ("check", ctypes.c_uint32)]
+                ("launch", ctypes.c_int32 * 5), ("check", ctypes.c_uint32)]
 
 
-PARAM_FIELDS = ("tile_cols_log2", "min_tiles", "chunk_pieces", "strip_columns", "piece_cap", "wgs_per_cu")
+PARAM_FIELDS = ("tile_cols_log2", "min_tiles", "chunk_pieces", "strip_columns", "piece_cap", "wgs_per_cu",
+                "cull_columns")
 PARAMS_SINGLE = 0
 PARAMS_BATCH = 1
 

@@ -173,6 +173,7 @@ tv::MeshTable make_table(const tv::CallSizes &c, uint8_t *ws, const tv::MeshDesc
     T.chunk = P.chunk ? P.chunk : tv::auto_chunk(c.nt, c.ntiles);
     T.strip = P.strip;
     T.piece_cap = P.piece_cap;
+    T.nocull = P.cull;
     T.accumulate = (flags & TV_ACCUMULATE) ? 1 : 0;
     T.nv_total = c.nv;
     T.nt_total = c.nt;
@@ -268,14 +269,15 @@ size_t single_ws_bytes(int64_t nv, int64_t nt, tv_dims dims, const tv::Params &P
 // tv_batch_prepare, or edited since).
 uint32_t plan_check(const tv_batch_plan &p) {
     uint64_t h = 0x9e3779b97f4a7c15ull;
-    const uint64_t v[8] = {(uint64_t)p.meshes,
+    const uint64_t v[9] = {(uint64_t)p.meshes,
                            (uint64_t)p.nv,
                            (uint64_t)p.nt,
                            (uint64_t)p.ntiles,
                            p.ws,
                            (uint64_t)p.flags,
                            (uint64_t)(uint32_t)p.launch[0] << 32 | (uint32_t)p.launch[1],
-                           (uint64_t)(uint32_t)p.launch[2] << 32 | (uint32_t)p.launch[3]};
+                           (uint64_t)(uint32_t)p.launch[2] << 32 | (uint32_t)p.launch[3],
+                           (uint64_t)(uint32_t)p.launch[4]};
     for (uint64_t x : v) {
         h ^= x + 0x9e3779b97f4a7c15ull + (h << 6) + (h >> 2);
         h *= 0xff51afd7ed558ccdull;
@@ -409,7 +411,7 @@ tv_status tv_default_params(int32_t which, tv_params *out) {
     if (!out || (which != TV_PARAMS_SINGLE && which != TV_PARAMS_BATCH))
         return fail(TV_ERR_INVALID_ARG, "params: need TV_PARAMS_SINGLE or TV_PARAMS_BATCH and an output");
     const tv::Params &P = which == TV_PARAMS_SINGLE ? tv::kDefaultSingle : tv::kDefaultBatch;
-    *out = {P.tile_cols_log2, P.min_tiles, P.chunk, P.strip, P.piece_cap, P.wgs_per_cu};
+    *out = {P.tile_cols_log2, P.min_tiles, P.chunk, P.strip, P.piece_cap, P.wgs_per_cu, P.cull};
     return TV_OK;
 }
 
@@ -417,7 +419,7 @@ tv_status tv_get_params(int32_t which, tv_params *out) {
     if (!out || (which != TV_PARAMS_SINGLE && which != TV_PARAMS_BATCH))
         return fail(TV_ERR_INVALID_ARG, "params: need TV_PARAMS_SINGLE or TV_PARAMS_BATCH and an output");
     const tv::Params P = current_params(which);
-    *out = {P.tile_cols_log2, P.min_tiles, P.chunk, P.strip, P.piece_cap, P.wgs_per_cu};
+    *out = {P.tile_cols_log2, P.min_tiles, P.chunk, P.strip, P.piece_cap, P.wgs_per_cu, P.cull};
     return TV_OK;
 }
 
@@ -439,8 +441,10 @@ tv_status tv_set_params(int32_t which, const tv_params *p) {
             return fail(TV_ERR_INVALID_ARG, "params: piece_cap %d not in [1,%d]", p->piece_cap, tv::kPieceCap);
         if (p->wgs_per_cu < 1 || p->wgs_per_cu > 8)
             return fail(TV_ERR_INVALID_ARG, "params: wgs_per_cu %d not in [1,8]", p->wgs_per_cu);
+        if (p->cull_columns < 0 || p->cull_columns > 1024)
+            return fail(TV_ERR_INVALID_ARG, "params: cull_columns %d not in [0,1024]", p->cull_columns);
         P = {p->tile_cols_log2, p->min_tiles, p->chunk_pieces, p->strip_columns, p->piece_cap,
-             p->wgs_per_cu};
+             p->wgs_per_cu, p->cull_columns};
     }
     std::lock_guard<std::mutex> lk(g_params_mu);
     g_params[which] = P;
@@ -478,6 +482,7 @@ tv_status tv_batch_prepare(const tv_mesh *meshes, int32_t n, void *ws, size_t ws
     plan->launch[1] = P.strip;
     plan->launch[2] = P.piece_cap;
     plan->launch[3] = P.wgs_per_cu;
+    plan->launch[4] = P.cull;
     plan->check = plan_check(*plan);
     return TV_OK;
 }
@@ -496,6 +501,7 @@ tv_status tv_batch_run(const tv_batch_plan *plan, void *ws, size_t ws_bytes, voi
     P.strip = plan->launch[1];
     P.piece_cap = plan->launch[2];
     P.wgs_per_cu = plan->launch[3];
+    P.cull = plan->launch[4];
     const tv::MeshTable T = make_table(c, w, nullptr, plan->flags, P);
     return enqueue(T, c, w, reinterpret_cast<hipStream_t>(stream), plan->flags, nullptr,
                    P.wgs_per_cu);

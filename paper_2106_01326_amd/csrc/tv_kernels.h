@@ -54,6 +54,7 @@ struct MeshTable {
     int32_t strip;      // kept columns per lane task
     int32_t piece_cap;  // tets meeting more tiles than this go to the large-tet kernel
     int32_t accumulate; // OR into the grids instead of overwriting them
+    int32_t nocull;     // boxes of at most this many columns skip row culling
     int64_t nv_total, nt_total, ntiles_total;
     MeshDesc one;
 };

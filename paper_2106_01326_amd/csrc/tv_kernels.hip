@@ -507,7 +507,6 @@ __device__ __forceinline__ int4 load_int4(gptr<int4> base, int64_t i) {
 constexpr int kTileThreads = 256;
 constexpr int kMaxTileWords = 4096;  // 16 KiB of LDS bitmap
 constexpr int kRowPool = 4096;       // per-batch row entries (16 KiB)
-constexpr uint32_t kNoCullColumns = 3;  // boxes of at most this many columns skip row culling
 
 struct PieceRec {
     Face f[4];
@@ -751,7 +750,7 @@ __global__ void __launch_bounds__(kTileThreads)
                 const uint32_t base = s_roff[tid];
                 uint32_t prefix = 0, kept = 0;
                 const uint32_t bw = (uint32_t)(hi[1] - lo[1] + 1);
-                if (nrows * bw <= kNoCullColumns) {
+                if (nrows * bw <= (uint32_t)T.nocull) {
                     // a box this small loses too little to culling to pay for it
                     for (uint32_t rr = 0; rr < nrows; ++rr) {
                         s_row[base + rr] = (bw << 8) | (rr << 16) | (prefix << 22);

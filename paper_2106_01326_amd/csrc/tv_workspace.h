@@ -22,13 +22,14 @@ struct Params {
     int32_t strip;           // kept columns per lane task
     int32_t piece_cap;       // tets meeting more tiles go to the large-tet kernel
     int32_t wgs_per_cu;      // persistent tile workgroups per compute unit
+    int32_t cull;            // boxes of at most this many columns skip row culling
 };
 // A lone grid wants >= 512 tiles to spread over the chip; batch meshes keep
 // the largest tiles (their parallelism comes from the mesh count).  chunk 0
 // sizes the queue tasks from the tet count (auto_chunk).  Values from the
 // autotuner's searches on the large, medium and batch workloads.
-constexpr Params kDefaultSingle = {5, 512, 0, 6, 8, 2};
-constexpr Params kDefaultBatch = {5, 1, 4096, 6, 8, 2};
+constexpr Params kDefaultSingle = {5, 512, 0, 6, 8, 2, 3};
+constexpr Params kDefaultBatch = {5, 1, 4096, 6, 8, 2, 6};
 
 // Pieces per work-queue task when Params::chunk is 0: about 4096 tasks in
 // all (pieces, about 2 per tet, / 4096 = nt / 2048), a power of two in

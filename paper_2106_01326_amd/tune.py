@@ -32,6 +32,7 @@ CANDIDATES = {
     "min_tiles": (256, 512, 1024, 2048),
     "piece_cap": (2, 4, 8),
     "wgs_per_cu": (1, 2, 3),
+    "cull_columns": (1, 3, 6, 12),
 }
 # fields not tuned for batch calls (each mesh keeps the largest tiles)
 BATCH_SKIP = ("min_tiles",)

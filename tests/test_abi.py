@@ -124,7 +124,9 @@ def test_launch_parameters(lib):
     """tv_params: defaults, validation (nothing changes on an error), reset,
     and workspace sizes that follow the tile fields."""
     assert tv.default_params("single") == {"tile_cols_log2": 5, "min_tiles": 512, "chunk_pieces": 0,
-                                           "strip_columns": 6, "piece_cap": 8, "wgs_per_cu": 2}
+                                           "strip_columns": 6, "piece_cap": 8, "wgs_per_cu": 2,
+                                           "cull_columns": 3}
+    assert tv.default_params("batch")["cull_columns"] == 6
     assert tv.default_params("batch")["min_tiles"] == 1
     try:
         base = tv.workspace_bytes(1000, 1000, (256, 256, 256))
@@ -136,7 +138,7 @@ def test_launch_parameters(lib):
         before = tv.get_params("single")
         for bad in ({"tile_cols_log2": 6}, {"tile_cols_log2": 2}, {"min_tiles": 0}, {"chunk_pieces": 63},
                     {"chunk_pieces": -1}, {"strip_columns": 0}, {"strip_columns": 65}, {"piece_cap": 9},
-                    {"wgs_per_cu": 0}):
+                    {"wgs_per_cu": 0}, {"cull_columns": -1}, {"cull_columns": 1025}):
             with pytest.raises(tv.TVError):
                 tv.set_params("single", **bad)
             assert tv.get_params("single") == before

@@ -24,6 +24,8 @@ SETTINGS = [
     {"min_tiles": 1 << 20},
     {"wgs_per_cu": 1},
     {"wgs_per_cu": 8},
+    {"cull_columns": 0},
+    {"cull_columns": 1024},
     {"tile_cols_log2": 3, "chunk_pieces": 64, "strip_columns": 3, "piece_cap": 1, "wgs_per_cu": 1},
 ]
 
