@@ -669,7 +669,10 @@ def bench_tune(args, torch, tv):
     from paper_2106_01326_amd import synth, tune
 
     dev = torch.device("cuda:0")
-    cache = os.path.join("gpurun_out", "tune_cache.json") if os.path.isdir("gpurun_out") else None
+    import tempfile
+
+    # a cache of its own, so that the run neither reads nor changes the user's
+    cache = os.path.join(tempfile.mkdtemp(prefix="tetvox_tune_"), "tune.json")
     res = {}
     for name in ("large", "medium"):
         log(f"generating workload {name}")

@@ -77,7 +77,9 @@ def _time(torch, fn, reps: int) -> float:
 def _search(torch, which: str, run, reps: int, fields, rounds: int = 1):
     """Coordinate search over `fields`.  `run()` makes one call with the
     parameters in force (reallocating its workspace when needed) and returns
-    its grids.  Returns (best params, ms of the defaults, ms of the best, log)."""
+    its grids.  Returns (best params, ms of the defaults, ms of the best, log);
+    the parameters in force before the search are restored afterwards."""
+    before = tv.get_params(which)
     tv.set_params(which, None)
     base = tv.get_params(which)
     ref = [g.clone() for g in run()]
@@ -104,7 +106,7 @@ def _search(torch, which: str, run, reps: int, fields, rounds: int = 1):
                     if ms < best_ms:
                         best, best_ms = trial, ms
     finally:
-        tv.set_params(which, None)
+        tv.set_params(which, before)
     return best, ms_default, best_ms, log
 
 
@@ -125,8 +127,8 @@ def _store(cache, key, entry):
 def tune_single(verts, tets, dims, bbox=None, qverts=False, reps=5, rounds=1, cache=None, store=True):
     """Tunes the single-mesh parameters on one mesh (device tensors).
     Returns {"key", "params", "ms_default", "ms_best", "log"}; the result is
-    written to the cache unless store is False.  The parameters in force are
-    restored to the defaults afterwards."""
+    written to the cache unless store is False.  The parameters in force
+    before the call are restored afterwards."""
     torch = tv._torch()
     nv, nt = int(verts.shape[0]), int(tets.shape[0])
     grid = tv.alloc_grid(dims, verts.device)

@@ -87,12 +87,14 @@ def test_autotuner_runs_and_caches(cases, tmp_path):
     cache = str(tmp_path / "tune.json")
     v, t, dims, bbox, _ = items[2]
     banner("tune_single on a 256^3 mesh")
+    tv.set_params("single", strip_columns=5)  # a setting of the caller's, restored after the search
     r = tune.tune_single(v, t, dims, bbox, reps=1, cache=cache)
+    assert tv.get_params("single") == dict(tv.default_params("single"), strip_columns=5)
+    tv.set_params("single", None)
     assert r["ms_best"] <= r["ms_default"]
     for f, val in r["params"].items():
         assert val == tv.default_params("single")[f] or val in tune.CANDIDATES[f]
     assert len(r["log"]) > 10
-    assert tv.get_params("single") == tv.default_params("single")  # restored
     assert tune.apply_cached("single", r["key"], cache)
     try:
         grid, _ = tv.voxelize(v, t, dims, bbox)
