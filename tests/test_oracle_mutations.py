@@ -35,6 +35,15 @@ MUTANTS = {
     "center_wrong_axis": ("(2 * k + 1) * S[2]", "(2 * k + 1) * S[1]"),
     "column_index_wrong_dim": ("int64_t col = i * J->n[1] + j;", "int64_t col = i * J->n[0] + j;"),
     "half_pitch_wrong": ("S[a] = (LATTICE / 2) / J->n[a];", "S[a] = LATTICE / J->n[a];"),
+    # the multithreaded split and merge (meshes of 4096 tets and more)
+    "thread_range_end_short": ("J->t1 = nt * (t + 1) / nthreads;", "J->t1 = nt * (t + 1) / nthreads - 1;"),
+    "thread_range_start_late": ("J->t0 = nt * t / nthreads;", "J->t0 = nt * t / nthreads + (t > 0);"),
+    "merge_skips_thread_1": ("        if (t > 0) {\n            for (int64_t w = 0;",
+                             "        if (t > 1) {\n            for (int64_t w = 0;"),
+    "merge_skips_last_word": ("for (int64_t w = 0; w < nwords; ++w) words[w] |= priv[t][w];",
+                              "for (int64_t w = 0; w + 1 < nwords; ++w) words[w] |= priv[t][w];"),
+    "status_of_thread_0_only": ("if (jobs[t].status != ORACLE_OK) status = jobs[t].status;",
+                                "if (t == 0 && jobs[t].status != ORACLE_OK) status = jobs[t].status;"),
     "snap_round_away": ("double r = nearbyint(t);", "double r = round(t);"),
     "snap_scale": ("t = t * 65536.0;", "t = t * 65535.0;"),
     "snap_range": ("if (r < (double)Q_LO || r > (double)Q_HI)", "if (r < (double)Q_LO - 1 || r > (double)Q_HI)"),
@@ -53,6 +62,10 @@ def run_pins(mod):
         ("brute", lambda: pins.test_aabb_culling_matches_brute_force(mod)),
         ("rationals", lambda: pins.test_whole_mesh_against_exact_rationals(mod)),
         ("translation", lambda: pins.test_translation_by_one_voxel(mod)),
+        ("mt_full_cube", lambda: [pins.test_full_cube_multithreaded_is_all_ones(mod, t) for t in (2, 3, 7)]),
+        ("mt_partition", lambda: pins.test_kept_and_complement_partition_multithreaded(mod, 2)),
+        ("mt_status", lambda: [pins.test_multithreaded_index_error_is_reported(mod, w)
+                               for w in ("first", "middle", "last")]),
         ("snap_exact", lambda: pins.test_snap_exact_cases(mod)),
         ("snap_range", lambda: pins.test_snap_range_and_nan(mod)),
     ]
@@ -60,7 +73,7 @@ def run_pins(mod):
     for name, fn in checks:
         try:
             fn()
-        except (AssertionError, oracle.OracleError, ValueError, IndexError):
+        except (AssertionError, oracle.OracleError, ValueError, IndexError, pytest.fail.Exception):
             failed.append(name)
     return failed
 

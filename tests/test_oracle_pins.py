@@ -218,6 +218,56 @@ def test_kept_and_complement_partition_the_cube(oracle_mod):
     assert 0 < a.sum() < a.size
 
 
+# The oracle splits a mesh of at least 4096 tets into per-thread tet ranges,
+# each voxelized into a private bitmap, and ORs the bitmaps together.  The
+# pins below run that branch on meshes whose answer the mathematics fixes,
+# so a tet dropped at a range boundary or a bitmap left out of the merge
+# leaves a hole that they see.
+
+@pytest.mark.parametrize("threads", [2, 3, 7, 16])
+def test_full_cube_multithreaded_is_all_ones(oracle_mod, threads):
+    """6,000 tets (10^3 cubes, the whole bbox) on 2 to 16 threads: a
+    conforming mesh of the bbox covers every center, so every bit is set;
+    each tet holds about 44 centers of the 64^3 grid, so a missing tet
+    leaves a hole."""
+    m = synth.make_mesh(10, 0.4, 64, "all", 0, 91)
+    assert m.nt == 6000
+    q = oracle_mod.snap(m.verts, *m.bbox)
+    w = oracle_mod.voxelize_q(q, m.tets, m.dims, threads=threads)
+    assert oracle_mod.unpack(w, m.dims).all()
+
+
+@pytest.mark.parametrize("threads", [2, 5])
+def test_kept_and_complement_partition_multithreaded(oracle_mod, threads):
+    """Kept ⊎ dropped tets of a 16^3-cube mesh (24,576 tets, both parts above
+    4096 tets) on several threads: disjoint, and together all ones."""
+    rng = np.random.default_rng(22)
+    pos, tets, _ = synth.jittered_kuhn(16, 0.4, rng, "f32")
+    q = oracle_mod.snap(pos, np.zeros(3, np.float32), np.ones(3, np.float32))
+    ell = synth.random_ellipsoids(3, rng)
+    keep = synth.keep_union_ellipsoids(synth.centroids_unit(pos, tets, "f32"), ell)
+    assert keep.sum() >= 4096 and (~keep).sum() >= 4096
+    dims = (64, 64, 64)
+    a = oracle_mod.unpack(oracle_mod.voxelize_q(q, tets[keep], dims, threads=threads), dims)
+    b = oracle_mod.unpack(oracle_mod.voxelize_q(q, tets[~keep], dims, threads=threads), dims)
+    assert not np.any(a & b)
+    assert np.all(a | b)
+
+
+@pytest.mark.parametrize("where", ["first", "middle", "last"])
+def test_multithreaded_index_error_is_reported(oracle_mod, where):
+    """A tet index outside [0, nv) is an error wherever it sits in a mesh
+    that the oracle splits over threads."""
+    m = synth.make_mesh(10, 0.3, 32, "all", 0, 92)
+    q = oracle_mod.snap(m.verts, *m.bbox)
+    tets = m.tets.copy()
+    pos = {"first": 0, "middle": m.nt // 2 + 1, "last": m.nt - 1}[where]
+    tets[pos, 2] = q.shape[0]
+    for threads in (1, 4, 8):
+        with pytest.raises(oracle_mod.OracleError):
+            oracle_mod.voxelize_q(q, tets, m.dims, threads=threads)
+
+
 def test_aabb_culling_matches_brute_force(oracle_mod):
     """Bounding-box scan (Section 3) == every center against every tet."""
     for m in (synth.workload_small(), synth.make_mesh(6, 0.4, 16, "ellipsoids", 2, 31)):
