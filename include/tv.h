@@ -269,8 +269,10 @@ const char *tv_profile_stage_name(int32_t stage);
  *
  *   - tv_server_create allocates, once, a device arena (inputs, grids and
  *     wave workspaces live in it) and a pinned host staging area, creates
- *     `streams` compute streams and starts a scheduler and a completion
- *     thread on the current device.
+ *     `streams` compute streams and starts, on the current device, a
+ *     scheduler thread, one launcher thread per stream (it stages host
+ *     inputs and enqueues the wave's copies and kernels, so admission never
+ *     waits for a copy) and a completion thread.
  *   - tv_server_submit queues a request (host or device inputs, see flags);
  *     the scheduler admits queued requests in FIFO order while their memory
  *     footprint (inputs + grid + workspace share) fits in the arena and a
@@ -315,6 +317,7 @@ typedef struct {
     int64_t running;          /* requests in waves on the device */
     int64_t inflight_waves;
     size_t device_in_use, device_peak, pinned_in_use;
+    int64_t inflight_peak;    /* most waves in flight at once so far */
 } tv_server_stats;
 
 #define TV_REQ_QUEUED 0

@@ -120,7 +120,7 @@ class ServerStatsC(ctypes.Structure):
                 ("rejected", ctypes.c_int64), ("waves", ctypes.c_int64), ("queued", ctypes.c_int64),
                 ("running", ctypes.c_int64), ("inflight_waves", ctypes.c_int64),
                 ("device_in_use", ctypes.c_size_t), ("device_peak", ctypes.c_size_t),
-                ("pinned_in_use", ctypes.c_size_t)]
+                ("pinned_in_use", ctypes.c_size_t), ("inflight_peak", ctypes.c_int64)]
 
 
 class TVError(RuntimeError):
