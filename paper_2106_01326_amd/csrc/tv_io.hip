@@ -10,6 +10,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <exception>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -58,6 +59,15 @@ struct Reader {
     bool at_end() {
         skip_space();
         return pos + 1 >= buf.size();
+    }
+    // Could the rest of the file hold n entries of `tokens` tokens each?
+    // Every token takes at least one byte, so a count above the bytes left
+    // (a corrupt or hostile header) is refused before anything is sized
+    // from it.
+    bool can_hold(int64_t n, int64_t tokens) const {
+        if (n < 0) return false;
+        const int64_t left = (int64_t)(buf.size() - pos);
+        return n <= left / tokens;
     }
     // next whitespace-delimited token (empty at the end)
     std::string token() {
@@ -124,7 +134,7 @@ tv_status read_medit(Reader &r, const char *path, Parsed &out) {
         } else if (kw == "Dimension") {
             if (!r.integer(n) || n != 3) return io_error(path, "only Dimension 3 is supported");
         } else if (kw == "Vertices") {
-            if (!r.integer(n) || n < 0) return io_error(path, "bad Vertices count");
+            if (!r.integer(n) || !r.can_hold(n, 4)) return io_error(path, "bad Vertices count");
             out.verts.resize((size_t)n * 3);
             for (int64_t i = 0; i < n; ++i) {
                 double x[3];
@@ -135,7 +145,7 @@ tv_status read_medit(Reader &r, const char *path, Parsed &out) {
             }
             have_v = true;
         } else if (kw == "Tetrahedra") {
-            if (!r.integer(n) || n < 0) return io_error(path, "bad Tetrahedra count");
+            if (!r.integer(n) || !r.can_hold(n, 5)) return io_error(path, "bad Tetrahedra count");
             out.tets.resize((size_t)n * 4);
             for (int64_t i = 0; i < n; ++i) {
                 int64_t v[5];
@@ -150,7 +160,7 @@ tv_status read_medit(Reader &r, const char *path, Parsed &out) {
         } else {
             const int per = medit_entry_tokens(kw);
             if (per < 0) return tv::set_error(TV_ERR_IO, "%s: unknown keyword '%s'", path, kw.c_str());
-            if (!r.integer(n) || n < 0) return io_error(path, "bad section count");
+            if (!r.integer(n) || !r.can_hold(n, per)) return io_error(path, "bad section count");
             for (int64_t i = 0; i < n * per; ++i)
                 if (r.token().empty()) return io_error(path, "truncated section");
             // other element kinds are counted as skipped; tags and normals are not elements
@@ -198,7 +208,7 @@ tv_status read_gmsh(Reader &r, const char *path, Parsed &out) {
         if (sec == "$Nodes") {
             if (v2) {
                 int64_t n;
-                if (!r.integer(n) || n < 0) return io_error(path, "bad $Nodes count");
+                if (!r.integer(n) || !r.can_hold(n, 4)) return io_error(path, "bad $Nodes count");
                 out.verts.reserve((size_t)n * 3);
                 for (int64_t i = 0; i < n; ++i) {
                     int64_t tag;
@@ -211,7 +221,8 @@ tv_status read_gmsh(Reader &r, const char *path, Parsed &out) {
                 }
             } else {
                 int64_t blocks, n, mn, mx;
-                if (!r.integer(blocks) || !r.integer(n) || !r.integer(mn) || !r.integer(mx))
+                if (!r.integer(blocks) || !r.integer(n) || !r.integer(mn) || !r.integer(mx) ||
+                    !r.can_hold(blocks, 4) || !r.can_hold(n, 4))
                     return io_error(path, "bad $Nodes header");
                 out.verts.reserve((size_t)n * 3);
                 for (int64_t b = 0; b < blocks; ++b) {
@@ -219,6 +230,7 @@ tv_status read_gmsh(Reader &r, const char *path, Parsed &out) {
                     if (!r.integer(edim) || !r.integer(etag) || !r.integer(param) || !r.integer(m))
                         return io_error(path, "bad node block header");
                     if (param) return io_error(path, "parametric nodes are not supported");
+                    if (!r.can_hold(m, 4)) return io_error(path, "bad node block size");
                     std::vector<int64_t> tags((size_t)m);
                     for (int64_t i = 0; i < m; ++i)
                         if (!r.integer(tags[(size_t)i])) return io_error(path, "truncated node tags");
@@ -237,7 +249,7 @@ tv_status read_gmsh(Reader &r, const char *path, Parsed &out) {
         } else if (sec == "$Elements") {
             if (v2) {
                 int64_t n;
-                if (!r.integer(n) || n < 0) return io_error(path, "bad $Elements count");
+                if (!r.integer(n) || !r.can_hold(n, 4)) return io_error(path, "bad $Elements count");
                 for (int64_t i = 0; i < n; ++i) {
                     int64_t tag, type, ntags;
                     if (!r.integer(tag) || !r.integer(type) || !r.integer(ntags) || ntags < 0)
@@ -255,7 +267,8 @@ tv_status read_gmsh(Reader &r, const char *path, Parsed &out) {
                 }
             } else {
                 int64_t blocks, n, mn, mx;
-                if (!r.integer(blocks) || !r.integer(n) || !r.integer(mn) || !r.integer(mx))
+                if (!r.integer(blocks) || !r.integer(n) || !r.integer(mn) || !r.integer(mx) ||
+                    !r.can_hold(blocks, 4) || !r.can_hold(n, 2))
                     return io_error(path, "bad $Elements header");
                 for (int64_t b = 0; b < blocks; ++b) {
                     int64_t edim, etag, type, m;
@@ -263,6 +276,7 @@ tv_status read_gmsh(Reader &r, const char *path, Parsed &out) {
                         return io_error(path, "bad element block header");
                     const int nn = gmsh_nodes_of_type(type);
                     if (nn < 0) return io_error(path, "unknown element type");
+                    if (!r.can_hold(m, 1 + nn)) return io_error(path, "bad element block size");
                     for (int64_t i = 0; i < m; ++i) {
                         int64_t tag;
                         if (!r.integer(tag)) return io_error(path, "truncated element block");
@@ -291,13 +305,7 @@ tv_status read_gmsh(Reader &r, const char *path, Parsed &out) {
     return TV_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-tv_status tv_read_mesh(const char *path, tv_host_mesh *out) {
-    if (!path || !out) return tv::set_error(TV_ERR_INVALID_ARG, "null path or output");
-    memset(out, 0, sizeof *out);
+tv_status read_mesh(const char *path, tv_host_mesh *out) {
     Reader r;
     if (!r.load(path)) return tv::set_error(TV_ERR_IO, "%s: cannot read", path);
     Parsed p;
@@ -321,7 +329,7 @@ tv_status tv_read_mesh(const char *path, tv_host_mesh *out) {
     out->tets = static_cast<int32_t *>(malloc(sizeof(int32_t) * (size_t)(4 * nt + 1)));
     if (!out->verts || !out->tets) {
         tv_free_host_mesh(out);
-        return tv::set_error(TV_ERR_INVALID_ARG, "%s: out of host memory", path);
+        return tv::set_error(TV_ERR_IO, "%s: out of host memory", path);
     }
     memcpy(out->verts, p.verts.data(), sizeof(float) * (size_t)(3 * nv));
     memcpy(out->tets, p.tets.data(), sizeof(int32_t) * (size_t)(4 * nt));
@@ -339,6 +347,28 @@ tv_status tv_read_mesh(const char *path, tv_host_mesh *out) {
         out->bbox.hi[a] = hi;
     }
     return TV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tv_status tv_read_mesh(const char *path, tv_host_mesh *out) {
+    if (!path || !out) return tv::set_error(TV_ERR_INVALID_ARG, "null path or output");
+    memset(out, 0, sizeof *out);
+    // no exception may cross the C ABI: a file too large for host memory is
+    // an I/O error like any other unreadable file
+    try {
+        const tv_status st = read_mesh(path, out);
+        if (st) tv_free_host_mesh(out);
+        return st;
+    } catch (const std::exception &e) {
+        tv_free_host_mesh(out);
+        return tv::set_error(TV_ERR_IO, "%s: %s", path, e.what());
+    } catch (...) {
+        tv_free_host_mesh(out);
+        return tv::set_error(TV_ERR_IO, "%s: cannot read", path);
+    }
 }
 
 void tv_free_host_mesh(tv_host_mesh *m) {

@@ -76,6 +76,26 @@ BAD = {
     "node.msh": "$MeshFormat\n2.2 0 8\n$EndMeshFormat\n$Nodes\n1\n1 0 0 0\n$EndNodes\n"
                 "$Elements\n1\n1 4 0 1 1 1 9\n$EndElements\n",
     "unknown.txt": "hello\n",
+    # counts that the rest of the file cannot hold (corrupt or hostile headers)
+    "huge_vertices.mesh": "MeshVersionFormatted 2\nDimension 3\nVertices\n4000000000000000000\n0 0 0 0\n",
+    "huge_tets.mesh": "MeshVersionFormatted 2\nDimension 3\nVertices\n1\n0 0 0 0\n"
+                      "Tetrahedra\n999999999999\n1 1 1 1 0\nEnd\n",
+    "negative_vertices.mesh": "MeshVersionFormatted 2\nDimension 3\nVertices\n-5\nEnd\n",
+    "huge_section.mesh": "MeshVersionFormatted 2\nDimension 3\nTriangles\n123456789012\n1 2 3 0\nEnd\n",
+    "huge_nodes_v22.msh": "$MeshFormat\n2.2 0 8\n$EndMeshFormat\n$Nodes\n9000000000000000000\n"
+                          "1 0 0 0\n$EndNodes\n",
+    "negative_block_v41.msh": "$MeshFormat\n4.1 0 8\n$EndMeshFormat\n$Nodes\n1 1 1 1\n3 1 0 -1\n"
+                              "1\n0 0 0\n$EndNodes\n",
+    "huge_block_v41.msh": "$MeshFormat\n4.1 0 8\n$EndMeshFormat\n$Nodes\n1 1 1 1\n"
+                          "3 1 0 4611686018427387904\n1\n0 0 0\n$EndNodes\n",
+    "huge_header_v41.msh": "$MeshFormat\n4.1 0 8\n$EndMeshFormat\n$Nodes\n1 -7 1 1\n3 1 0 1\n"
+                           "1\n0 0 0\n$EndNodes\n",
+    "negative_elements_v22.msh": "$MeshFormat\n2.2 0 8\n$EndMeshFormat\n$Nodes\n1\n1 0 0 0\n$EndNodes\n"
+                                 "$Elements\n-3\n$EndElements\n",
+    "huge_element_block_v41.msh": "$MeshFormat\n4.1 0 8\n$EndMeshFormat\n$Nodes\n1 1 1 1\n3 1 0 1\n"
+                                  "1\n0 0 0\n$EndNodes\n$Elements\n1 1 1 1\n3 1 4 99999999999999\n"
+                                  "1 1 1 1 1\n$EndElements\n",
+    "truncated_v41.msh": "$MeshFormat\n4.1 0 8\n$EndMeshFormat\n$Nodes\n1 2 1 2\n3 1 0 2\n1\n2\n0 0 0\n",
 }
 
 
