@@ -49,16 +49,92 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+# Synthetic inputs are generated once per process and before the process
+# touches the GPU (see pregenerate); the worker pools that build many meshes
+# start fresh processes.
+_MESHES = {}
+
+
+def _memo(key, fn):
+    if key not in _MESHES:
+        t0 = time.perf_counter()
+        _MESHES[key] = fn()
+        log(f"generated {key} in {time.perf_counter() - t0:.1f} s")
+    return _MESHES[key]
+
+
 def make_workload(name):
     from paper_2106_01326_amd import synth
 
-    if name == "large":
-        return synth.workload_large()
-    if name == "medium":
-        return synth.workload_medium()
-    if name == "small":
-        return synth.workload_small()
-    raise SystemExit(f"unknown workload {name}")
+    gen = {"large": synth.workload_large, "medium": synth.workload_medium, "small": synth.workload_small}
+    if name not in gen:
+        raise SystemExit(f"unknown workload {name}")
+    return _memo(name, gen[name])
+
+
+def batch_meshes(count):
+    from paper_2106_01326_amd import synth
+
+    return _memo(f"batch{count}", lambda: synth.workload_batch(count=count, workers=gen_workers()))
+
+
+def serving_pool():
+    """512 batch-distribution meshes (seed 4) and 32 medium-shape fp32
+    meshes (seeds drawn from the same stream as the arrivals)."""
+    from paper_2106_01326_amd import synth
+
+    def make():
+        rng = np.random.default_rng(4)
+        small = synth.workload_batch(count=512, seed=4, workers=gen_workers())
+        seeds = [int(x) for x in rng.integers(0, 2**31, size=32)]
+        big = synth.pool_map(synth.medium_shape_fp32, seeds, gen_workers())
+        return small + big
+
+    return _memo("serving_pool", make)
+
+
+def gen_workers():
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    w = int(os.environ.get("TV_BENCH_GEN_WORKERS", "0")) or min(16, n)
+    return max(1, w)
+
+
+def host_cores():
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    return max(1, min(n, 16))
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def pregenerate(args):
+    """Builds every synthetic input the chosen workload uses, before the
+    first GPU call."""
+    w = args.workload
+    if w in ("large", "medium", "small"):
+        make_workload(w)
+        if w == "large" and not args.no_extras:
+            batch_meshes(args.batch_meshes)
+            serving_pool()
+    elif w == "batch":
+        batch_meshes(args.batch_meshes)
+    elif w == "serving":
+        serving_pool()
+    elif w in ("grids", "quality"):
+        make_workload("large")
+        if w == "quality":
+            make_workload("medium")
+    elif w == "tune":
+        make_workload("large")
+        make_workload("medium")
+        batch_meshes(args.batch_meshes)
 
 
 def workload_config(name, m):
@@ -110,14 +186,25 @@ def traffic_from_profiles(workload):
     return rec.get("hbm_bytes_per_launch")
 
 
+def valu_counters_from_profiles(workload, kept_columns=None):
+    """VALU counters of the tile kernel from the committed rocprofv3 --pmc
+    summary, or None when absent or taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"valu_voxelize_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    return rec.get("summary")
+
+
 def cpu_baseline(m, gpu_words_fn, target_s=12.0):
     """The oracle, as it stands, on a bounded sample (the first tets of the
     mesh), on all host cores; the GPU path runs the same sample and the two
     grids are compared bit for bit."""
     import oracle
 
-    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    cores = max(1, min(cores, 16))
+    cores = host_cores()
     q = oracle.snap(m.verts, *m.bbox) if m.verts is not None else m.qverts
     # grow the sample until one run takes about target_s: a short probe
     # underestimates the rate (grid clearing and thread start-up dominate it)
@@ -135,9 +222,16 @@ def cpu_baseline(m, gpu_words_fn, target_s=12.0):
         n = int(min(m.nt, n * min(16.0, max(2.0, 0.9 * target_s / max(dt, 1e-6)))))
     got = gpu_words_fn(sample)
     exact = bool(np.array_equal(got, want))
+    # one thread, on a sample sized for about a third of target_s
+    n1 = max(1000, min(m.nt, int(n / dt * target_s / 3 / cores)))
+    t0 = time.perf_counter()
+    oracle.voxelize_q(q if m.verts is None else oracle.snap(m.verts, *m.bbox), m.tets[:n1], m.dims, threads=1)
+    dt1 = time.perf_counter() - t0
     return {"value": n / dt, "unit": "tets/s", "cores": cores, "kind": "oracle",
             "sample": f"first {n} of {m.nt} tets (snap + voxelize, {dt:.1f} s wall)",
-            "seconds": dt, "gpu_bit_exact_on_sample": exact}
+            "seconds": dt, "gpu_bit_exact_on_sample": exact,
+            "value_1thread": n1 / dt1, "sample_1thread": f"first {n1} tets on one thread ({dt1:.1f} s wall)",
+            "cpu_model": cpu_model(), "host_cpus_visible": os.cpu_count()}
 
 
 def tile_roofline(torch, tv, items, meshes, vox_ms):
@@ -159,36 +253,30 @@ def tile_roofline(torch, tv, items, meshes, vox_ms):
             "units": {"tets_nonempty": ne, "candidate_columns": cols}}
 
 
-def bench_batch(args, torch, tv):
+def batch_core(args, torch, tv, meshes, steps, warmup, cpu=True):
     """Batched voxelization of the uneven batch vs a loop of single-mesh
     calls (the per-mesh baseline: back to back on one stream, one final
-    sync -- its best case)."""
-    from paper_2106_01326_amd import synth
-
-    log(f"generating {args.batch_meshes} meshes")
-    t0 = time.perf_counter()
-    meshes = synth.workload_batch(count=args.batch_meshes)
+    sync -- its best case); returns the measurements as a dict."""
     nt = sum(m.nt for m in meshes)
-    log(f"generated {len(meshes)} meshes, {nt} tets in {time.perf_counter() - t0:.1f} s")
     dev = torch.device("cuda:0")
     items = [(torch.from_numpy(m.verts).to(dev), torch.from_numpy(m.tets).to(dev), m.dims, m.bbox, False)
              for m in meshes]
     stream = torch.cuda.current_stream()
     batch = tv.Batch(items)
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         batch.run(stream=stream)
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record(stream)
-    for _ in range(args.steps):
+    for _ in range(steps):
         batch.run(stream=stream)
     ev1.record(stream)
     torch.cuda.synchronize()
-    ms_batch = ev0.elapsed_time(ev1) / args.steps
+    ms_batch = ev0.elapsed_time(ev1) / steps
     # stage times from a separate profiled pass
     tv.profile_read()
     tv.profile_enable(True)
-    for _ in range(max(2, min(args.steps, 5))):
+    for _ in range(max(2, min(steps, 5))):
         batch.run(stream=stream)
     torch.cuda.synchronize()
     tv.profile_enable(False)
@@ -210,11 +298,11 @@ def bench_batch(args, torch, tv):
     graph.replay()
     torch.cuda.synchronize()
     ev0.record(stream)
-    for _ in range(args.steps):
+    for _ in range(steps):
         graph.replay()
     ev1.record(stream)
     torch.cuda.synchronize()
-    ms_graph = ev0.elapsed_time(ev1) / args.steps
+    ms_graph = ev0.elapsed_time(ev1) / steps
     graph_same = all(torch.equal(a, b) for a, b in zip(ref, batch.grids))
     del graph, ref
     log(f"graph replay of the prepared batch: {ms_graph:.3f} ms per batch; identical={graph_same}")
@@ -229,7 +317,7 @@ def bench_batch(args, torch, tv):
 
     loop()
     torch.cuda.synchronize()
-    reps = max(1, min(3, args.steps))
+    reps = max(1, min(3, steps))
     t0 = time.perf_counter()
     ev0.record(stream)
     for _ in range(reps):
@@ -240,54 +328,63 @@ def bench_batch(args, torch, tv):
     wall_loop = (time.perf_counter() - t0) * 1e3 / reps
     same = all(torch.equal(a, b) for a, b in zip(grids, batch.grids))
     log(f"per-mesh loop: {ms_loop:.3f} ms per pass (host wall {wall_loop:.3f} ms); identical={same}")
-
-    out = {"metric": "meshes/s (batched)", "value": len(meshes) / (ms_batch * 1e-3), "unit": "meshes/s",
-           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_batch,
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
-           "data": "synthetic (seeded jittered Kuhn meshes)",
-           "config": {"workload": "uneven batch of small meshes", "meshes": len(meshes), "tets": nt,
-                      "grids": "32^3 or 64^3", "vert_format": "f32"},
-           "tets_per_s": nt / (ms_batch * 1e-3),
+    res = {"meshes": len(meshes), "tets": nt, "ms_per_batch": ms_batch,
+           "meshes_per_s": len(meshes) / (ms_batch * 1e-3), "tets_per_s": nt / (ms_batch * 1e-3),
            "per_mesh_loop": {"meshes_per_s": len(meshes) / (ms_loop * 1e-3), "ms_per_pass": ms_loop,
                              "host_wall_ms_per_pass": wall_loop},
            "batched_over_per_mesh": ms_loop / ms_batch, "bit_identical_to_per_mesh": bool(same),
            "graph_replay": {"ms_per_batch": ms_graph, "meshes_per_s": len(meshes) / (ms_graph * 1e-3),
                             "bit_identical": bool(graph_same)},
            "stage_ms": {k: v_ / max(calls, 1) for k, v_ in stages.items()}}
-    out["roofline"] = tile_roofline(torch, tv, items, meshes, stages.get("voxelize", 0.0) / max(calls, 1))
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline_batch(meshes, batch, args.cpu_seconds)
-    else:
-        out["cpu_baseline"] = None
+    res["roofline"] = tile_roofline(torch, tv, items, meshes, stages.get("voxelize", 0.0) / max(calls, 1))
+    if cpu:
+        res["cpu_baseline"] = cpu_baseline_batch(meshes, batch, args.cpu_seconds)
+    del grids, wss, items, batch
+    return res
+
+
+def bench_batch(args, torch, tv):
+    """The uneven batch workload as its own line (meshes/s batched)."""
+    meshes = batch_meshes(args.batch_meshes)
+    r = batch_core(args, torch, tv, meshes, args.steps, args.warmup, cpu=not args.no_cpu_baseline)
+    out = {"metric": "meshes/s (batched)", "value": r["meshes_per_s"], "unit": "meshes/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_batch"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic (seeded jittered Kuhn meshes)",
+           "config": {"workload": "uneven batch of small meshes", "meshes": len(meshes), "tets": r["tets"],
+                      "grids": "32^3 or 64^3", "vert_format": "f32"}}
+    for k in ("tets_per_s", "per_mesh_loop", "batched_over_per_mesh", "bit_identical_to_per_mesh",
+              "graph_replay", "stage_ms", "roofline"):
+        out[k] = r[k]
+    out["cpu_baseline"] = r.get("cpu_baseline")
     print(json.dumps(out), flush=True)
 
 
-def bench_serving(args, torch, tv):
-    """Poisson arrivals through the server; inputs are pre-staged in pinned
+def serving_core(args, torch, tv, pool_meshes, runs=3):
+    """Poisson arrivals through the server.  Inputs are pre-staged in pinned
     host memory (as a serving front end receiving into pinned buffers
-    would), grids stay on the device until the client releases them."""
+    would); grids stay on the device until the client releases them.
+
+    Sustained capacity is the highest offered Poisson rate, on a grid of
+    rates, that the server keeps up with (achieved >= 97% of offered over
+    the run); p50/p99 are then measured at 0.5/0.7/0.9 x that rate, `runs`
+    times each.  The same measurement with the inputs already in device
+    memory tests how much of the capacity the host-to-device copies set."""
+    import gc
     import threading
 
-    from paper_2106_01326_amd import synth
-
     rng = np.random.default_rng(4)
-    log("generating the request pool (512 batch-distribution + 32 medium-shape meshes)")
-    t0 = time.perf_counter()
-    small = synth.workload_batch(count=512, seed=4)
-    import multiprocessing as mp
-
-    with mp.get_context("fork").Pool(16) as pool:
-        big = pool.map(synth.medium_shape_fp32, [int(x) for x in rng.integers(0, 2**31, size=32)])
-    log(f"pool ready in {time.perf_counter() - t0:.1f} s")
-    pool_meshes = small + big
-    staged = [(torch.from_numpy(m.verts).pin_memory(), torch.from_numpy(m.tets).pin_memory(), m)
+    dev = torch.device("cuda:0")
+    pinned = [(torch.from_numpy(m.verts).pin_memory(), torch.from_numpy(m.tets).pin_memory(), m)
               for m in pool_meshes]
+    device = [(v.to(dev), t.to(dev), m) for v, t, m in pinned]
+    torch.cuda.synchronize()
 
     def draw(n):
         pick_big = rng.random(n) < 0.1
         return [int(rng.integers(512, 544)) if b else int(rng.integers(0, 512)) for b in pick_big]
 
-    def run_stream(srv, arrivals, picks):
+    def run_stream(srv, staged, inputs, arrivals, picks):
         tickets = [None] * len(picks)
         lat = [0.0] * len(picks)
         done_t = [0.0] * len(picks)
@@ -305,6 +402,8 @@ def bench_serving(args, torch, tv):
                 srv.release(tickets[i])
 
         th = threading.Thread(target=collector)
+        gc.collect()
+        gc.disable()  # no collector pauses inside the timed stream
         th.start()
         lag = np.zeros(len(picks))
         start = time.perf_counter()
@@ -319,50 +418,83 @@ def bench_serving(args, torch, tv):
                     time.sleep(d - 2e-4)
             v, t, m = staged[k]
             lag[i] = time.perf_counter() - start - a
-            tickets[i] = srv.submit(v, t, m.dims, m.bbox, inputs="pinned")
+            tickets[i] = srv.submit(v, t, m.dims, m.bbox, inputs=inputs)
         th.join()
+        gc.enable()
         span = max(done_t) - start
-        return np.array(lat), span, stats["ok"], lag
+        assert stats["ok"] == len(picks), f"{len(picks) - stats['ok']} requests failed"
+        return np.array(lat), span, lag
 
-    res = {}
+    def poisson(srv, staged, inputs, rate, n):
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n))
+        lat, span, lag = run_stream(srv, staged, inputs, arrivals, draw(n))
+        return {"offered_meshes_per_s": rate, "achieved_meshes_per_s": n / span, "requests": n,
+                "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                "mean_ms": float(lat.mean() * 1e3), "submit_lag_p99_ms": float(np.percentile(lag, 99) * 1e3)}
+
+    def measure(staged, inputs):
+        res = {}
+        with tv.Server(device_bytes=32 << 30, pinned_bytes=0, streams=2, max_wave_meshes=256) as srv:
+            run_stream(srv, staged, inputs, np.zeros(64), draw(64))  # warm-up
+            nb = min(args.requests, 4000)
+            lat, span, _ = run_stream(srv, staged, inputs, np.zeros(nb), draw(nb))
+            burst = nb / span
+            res["burst_capacity_meshes_per_s"] = burst
+            # sustained capacity: rising Poisson rates until the server falls behind
+            probes = []
+            sustained = None
+            for f in (0.5, 0.6, 0.7, 0.8, 0.9, 1.0, 1.1, 1.25):
+                r = poisson(srv, staged, inputs, f * burst, min(args.requests, 6000))
+                keeps_up = r["achieved_meshes_per_s"] >= 0.97 * r["offered_meshes_per_s"]
+                probes.append([round(r["offered_meshes_per_s"]), round(r["achieved_meshes_per_s"]),
+                               round(r["p99_ms"], 3)])
+                if not keeps_up:
+                    break
+                sustained = r["offered_meshes_per_s"]
+            sustained = sustained or 0.5 * burst
+            res["sustained_capacity_meshes_per_s"] = sustained
+            res["capacity_probes_offered_achieved_p99"] = probes
+            log(f"{inputs} inputs: burst {burst:.0f}, sustained {sustained:.0f} meshes/s; probes {probes}")
+            for frac in (0.5, 0.7, 0.9):
+                rs = [poisson(srv, staged, inputs, frac * sustained, args.requests) for _ in range(runs)]
+                agg = {"offered_meshes_per_s": frac * sustained, "requests_per_run": args.requests, "runs": runs}
+                for key in ("p50_ms", "p99_ms", "achieved_meshes_per_s", "submit_lag_p99_ms"):
+                    vals = sorted(r[key] for r in rs)
+                    agg[key] = vals[len(vals) // 2]
+                    agg[key + "_min_max"] = [vals[0], vals[-1]]
+                agg["achieved_over_offered"] = agg["achieved_meshes_per_s"] / agg["offered_meshes_per_s"]
+                log(f"{inputs} inputs, lambda={frac:.1f} x sustained: {agg}")
+                res[f"lambda_{frac:.1f}"] = agg
+            res["server_stats"] = {k: int(v) for k, v in srv.stats().items()}
+        return res
+
     # a short switch interval keeps the collector thread from waiting behind
     # the submitting thread for the interpreter lock
     switch = sys.getswitchinterval()
     sys.setswitchinterval(2e-4)
-    with tv.Server(device_bytes=32 << 30, pinned_bytes=0, streams=2, max_wave_meshes=256) as srv:
-        # warm up, then capacity: a burst of requests all arriving at once
-        run_stream(srv, np.zeros(64), draw(64))
-        nb = min(args.requests, 4000)
-        picks = draw(nb)
-        lat, span, ok, _ = run_stream(srv, np.zeros(nb), picks)
-        cap = nb / span
-        log(f"capacity (burst of {nb}): {cap:.0f} meshes/s, p50 {np.median(lat)*1e3:.2f} ms")
-        res["capacity_meshes_per_s"] = cap
-        for frac in (0.5, 0.7, 0.9):
-            rate = frac * cap
-            n = args.requests
-            arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n))
-            picks = draw(n)
-            lat, span, ok, lag = run_stream(srv, arrivals, picks)
-            r = {"offered_meshes_per_s": rate, "achieved_meshes_per_s": n / span, "requests": n,
-                 "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
-                 "mean_ms": float(lat.mean() * 1e3), "ok": int(ok),
-                 "submit_lag_p99_ms": float(np.percentile(lag, 99) * 1e3)}
-            log(f"lambda={frac:.1f} x capacity: {r}")
-            res[f"lambda_{frac:.1f}"] = r
-        st = srv.stats()
-    sys.setswitchinterval(switch)
+    try:
+        out = measure(pinned, "pinned")
+        out["device_inputs"] = measure(device, "device")
+    finally:
+        sys.setswitchinterval(switch)
+    del device
+    return out
+
+
+def bench_serving(args, torch, tv):
+    """The serving workload as its own line (p99 at 0.9 x sustained capacity)."""
+    res = serving_core(args, torch, tv, serving_pool())
     top = res["lambda_0.9"]
-    out = {"metric": "p99 latency (serving, 0.9 x capacity)", "value": top["p99_ms"], "unit": "ms",
-           "n_gpus": 1, "steps": args.requests, "warmup": 64, "ms_per_step": top["mean_ms"],
+    out = {"metric": "p99 latency (serving, 0.9 x sustained capacity)", "value": top["p99_ms"], "unit": "ms",
+           "n_gpus": 1, "steps": args.requests, "warmup": 64, "ms_per_step": None,
            "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
            "data": "synthetic (seeded jittered Kuhn meshes)",
            "config": {"workload": "Poisson request stream", "mix": "90% batch distribution, 10% medium shape",
-                      "pool": "512 + 32 meshes", "inputs": "pinned host memory", "streams": 2},
-           "serving": res, "server_stats": {k: int(v) for k, v in st.items()},
-           "roofline": None,
-           "roofline_note": "bound by the host-to-device copies of the requests' inputs over PCIe, not by a "
-                            "kernel (the device-resident rates are in the batch and sweep lines)",
+                      "pool": "512 + 32 meshes", "inputs": "pinned host memory (device inputs alongside)",
+                      "streams": 2},
+           "serving": res, "roofline": None,
+           "roofline_note": "the served rate is set by the host-to-device copies of the requests' inputs "
+                           "(compare the device-input capacity), not by a kernel",
            "cpu_baseline": None}
     print(json.dumps(out), flush=True)
 
@@ -633,8 +765,7 @@ def cpu_baseline_batch(meshes, batch, target_s):
     wall time; compared bit for bit with the batched GPU grids."""
     import oracle
 
-    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    cores = max(1, min(cores, 16))
+    cores = host_cores()
     t0 = time.perf_counter()
     n = 0
     tets = 0
@@ -687,7 +818,7 @@ def bench_tune(args, torch, tv):
         log(f"{name}: default {r['ms_default']:.4f} ms, tuned {r['ms_best']:.4f} ms with {r['params']}")
         del v, t
     log(f"generating {args.batch_meshes} batch meshes")
-    meshes = synth.workload_batch(count=args.batch_meshes)
+    meshes = batch_meshes(args.batch_meshes)
     items = [(torch.from_numpy(m.verts).to(dev), torch.from_numpy(m.tets).to(dev), m.dims, m.bbox, False)
              for m in meshes]
     r = tune.tune_batch(tv.Batch(items), reps=3, rounds=2, cache=cache)
@@ -721,6 +852,9 @@ def main():
     ap.add_argument("--batch-meshes", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="large workload only: skip the batch and serving measurements that the "
+                         "default line carries next to the headline")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="before the workload, run one plain device copy of this many MiB so "
                          "that a hardware-counter run can scale its byte counters")
@@ -730,6 +864,10 @@ def main():
         print("bench.py runs on exactly one GPU: the voxelizer is a single-GPU build "
               "(multi-GPU sharding is a design note only); use --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    # every synthetic input first: nothing below may fork or spawn workers
+    # once the process has touched the GPU
+    pregenerate(args)
 
     import torch
 
@@ -759,10 +897,8 @@ def main():
         return bench_sweep(args, torch, tv)
     if args.workload == "tune":
         return bench_tune(args, torch, tv)
-    log(f"generating workload {args.workload}")
-    t0 = time.perf_counter()
     m = make_workload(args.workload)
-    log(f"generated nt={m.nt} nv={m.nv} in {time.perf_counter() - t0:.1f} s")
+    log(f"workload {args.workload}: nt={m.nt} nv={m.nv}")
 
     dev = torch.device("cuda:0")
     qverts = m.verts is None
@@ -840,6 +976,26 @@ def main():
         out["cpu_baseline"] = cpu_baseline(m, gpu_words, args.cpu_seconds)
     else:
         out["cpu_baseline"] = None
+    out["valu_counters"] = valu_counters_from_profiles(args.workload, n_cols)
+    del v, t, grid, ws
+    if args.workload == "large" and not args.no_extras:
+        # the rest of the metric: batched vs per-mesh meshes/s on the uneven
+        # batch, and serving latency percentiles
+        log("batch workload (1024 uneven meshes)")
+        torch.cuda.empty_cache()
+        b = batch_core(args, torch, tv, batch_meshes(args.batch_meshes), steps=10, warmup=2,
+                       cpu=not args.no_cpu_baseline)
+        out["batch"] = {k: b[k] for k in ("meshes", "tets", "ms_per_batch", "meshes_per_s", "tets_per_s",
+                                          "per_mesh_loop", "batched_over_per_mesh",
+                                          "bit_identical_to_per_mesh", "graph_replay", "stage_ms")}
+        out["batch"]["roofline_frac"] = b["roofline"]["frac"]
+        if b.get("cpu_baseline"):
+            out["batch"]["oracle_bit_exact_on_sample"] = b["cpu_baseline"]["gpu_bit_exact_on_sample"]
+            out["batch"]["cpu_baseline"] = b["cpu_baseline"]
+        log("serving workload (Poisson arrivals)")
+        torch.cuda.empty_cache()
+        sv = serving_core(args, torch, tv, serving_pool())
+        out["serving"] = sv
     print(json.dumps(out), flush=True)
 
 

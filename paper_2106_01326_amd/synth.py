@@ -337,10 +337,25 @@ def workload_batch(count: int = 1024, seed: int = 3, first: int | None = None,
         workers = min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else 1)
     if workers <= 1 or len(ps) < 8:
         return [batch_mesh(p) for p in ps]
+    return pool_map(batch_mesh, ps, workers, chunksize=4)
+
+
+def pool_map(fn, items, workers: int, chunksize: int = 1):
+    """``map`` over worker processes started fresh ("spawn"): a caller that
+    has already initialised the GPU never forks its own state into them.
+    The pool is closed and joined, so its workers end normally."""
     import multiprocessing as mp
 
-    with mp.get_context("fork").Pool(workers) as pool:
-        return pool.map(batch_mesh, ps, chunksize=4)
+    pool = mp.get_context("spawn").Pool(workers)
+    try:
+        out = pool.map(fn, items, chunksize=chunksize)
+        pool.close()
+    except BaseException:
+        pool.terminate()
+        raise
+    finally:
+        pool.join()
+    return out
 
 
 def medium_shape_fp32(seed) -> Mesh:

@@ -59,6 +59,24 @@ def test_batch_matches_oracle_and_solo(oracle_mod, uneven, per_tet):
         assert np.array_equal(to_numpy_words(g), to_numpy_words(grids[i]))
 
 
+def test_full_batch_workload_every_mesh(oracle_mod):
+    """The whole uneven batch workload (1024 meshes, 32^3 and 64^3 grids,
+    fp32 input) in one batched call: every mesh's grid against the oracle."""
+    import paper_2106_01326_amd as tv
+
+    ms = synth.workload_batch(count=1024, workers=8)
+    banner(f"full batch workload: {len(ms)} meshes, {sum(m.nt for m in ms)} tets")
+    b = tv.Batch([to_item(m) for m in ms])
+    for g in b.grids:
+        g.fill_(-1)
+    grids = b.run()
+    bad = []
+    for i, (m, g) in enumerate(zip(ms, grids)):
+        if b.status(i) != tv.TV_OK or not np.array_equal(to_numpy_words(g), oracle_mod.voxelize_mesh(m)):
+            bad.append(i)
+    assert not bad, f"{len(bad)} meshes differ, first {bad[:5]}"
+
+
 def test_batch_rerun_and_strict(oracle_mod, uneven):
     import paper_2106_01326_amd as tv
 

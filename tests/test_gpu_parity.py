@@ -17,6 +17,15 @@ def banner(msg):
     print(f"[case] {msg}", flush=True)
 
 
+def oracle_threads():
+    """Host threads for full-size oracle runs: the machine's CPU share (16), or
+    fewer where the machine has fewer."""
+    import os
+
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    return max(1, min(16, n))
+
+
 def oracle_words(oracle_mod, mesh, strict=False, **kw):
     return oracle_mod.voxelize_mesh(mesh, mode=STRICT if strict else HALF, **kw)
 
@@ -308,6 +317,17 @@ def test_many_tets_full_grid(oracle_mod):
     got, st = gpu_voxelize_mesh(m)
     assert st == 0
     assert_same(got, oracle_words(oracle_mod, m), "many tets")
+
+
+def test_large_workload_full_grid(oracle_mod, large):
+    """The whole 1024^3 grid of the large workload (5.56M tets, fp32 input
+    snapped on the device) against the oracle over every tet, bit for bit."""
+    banner(f"large workload full grid nt={large.nt} nv={large.nv}")
+    got, st = gpu_voxelize_mesh(large)
+    assert st == 0
+    want = oracle_words(oracle_mod, large, threads=oracle_threads())
+    assert_same(got, want, "large (full grid)")
+    assert int(np.unpackbits(want.view(np.uint8)).sum()) > 0
 
 
 def test_large_workload_sampled_windows(oracle_mod, large):

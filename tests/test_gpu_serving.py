@@ -148,3 +148,24 @@ def test_input_modes_and_strict(oracle_mod, mix):
         assert np.array_equal(grid_of(srv, tb, m.dims), oracle_mod.voxelize_mesh(m))
         with pytest.raises(tv.TVError):
             srv.release(987654)
+
+
+def test_waves_overlap_on_the_device(oracle_mod, mix):
+    """A long request (a 256^3 grid) followed at once by small ones, with two
+    streams and small waves: a second wave is launched while the first is
+    still on the device, so at least two waves are in flight together."""
+    import paper_2106_01326_amd as tv
+
+    long_req = [m for m in mix if m.dims[0] == 256][0]
+    small = [m for m in mix if m.dims[0] <= 64][:24]
+    with tv.Server(device_bytes=2 << 30, pinned_bytes=256 << 20, streams=2, max_wave_meshes=4) as srv:
+        banner("overlap: one 256^3 request then 24 small ones")
+        tickets = [submit_mesh(srv, long_req)] + [submit_mesh(srv, m) for m in small]
+        for t, m in zip(tickets, [long_req] + small):
+            srv.wait(t, timeout=60)
+            assert srv.result(t)[2] == tv.TV_OK
+            assert np.array_equal(grid_of(srv, t, m.dims), oracle_mod.voxelize_mesh(m))
+            srv.release(t)
+        s = srv.stats()
+        assert s["waves"] >= 2
+        assert s["inflight_peak"] >= 2, s
