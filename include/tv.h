@@ -125,6 +125,30 @@ tv_status tv_voxelize_q(const int32_t *qverts, int64_t nv, const int32_t *tets, 
                         uint32_t flags);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): tv_voxelize
+ * with no workspace argument.  The scratch space is a fixed device array of
+ * TV_NOALLOC_MAX_BYTES inside the library, one per GPU, held from the first
+ * call on that GPU until the process ends; the call itself allocates nothing.
+ *   verts, nv, tets, nt, dims, bbox, grid   as for tv_voxelize
+ *   status_out  device int32 (may be NULL): receives the call's data-error
+ *               status (TV_OK, TV_ERR_INDEX or TV_ERR_RANGE) on `stream`
+ *   flags       0 or TV_TIE_STRICT (nothing else)
+ * A mesh whose workspace (tv_workspace_bytes) exceeds TV_NOALLOC_MAX_BYTES
+ * (about 1.4 million tets at one vertex per five tets) is refused with TV_ERR_WORKSPACE and nothing is
+ * enqueued.  Every call on one GPU shares that GPU's array: calls that
+ * overlap on the device (different streams, or different host threads without
+ * ordering) race and give undefined results; calls ordered on one stream are
+ * safe.  Each call clears the parts of the array it needs zeroed.  The call
+ * must be made with the grid's device current.  Like tv_voxelize it enqueues
+ * kernels only, so it can be captured in a HIP graph.
+ */
+#define TV_NOALLOC_MAX_BYTES ((size_t)64 << 20)
+tv_status tv_voxelize_noalloc(const float *verts, int64_t nv, const int32_t *tets, int64_t nt,
+                              tv_dims dims, tv_bbox bbox, uint32_t *grid, int32_t *status_out,
+                              void *stream, uint32_t flags);
+
+/*
  * Batches: many meshes of uneven size voxelized by one launch sequence
  * (each mesh into its own grid).  `meshes` is a HOST array of n descriptors
  * whose pointers are device pointers; vert_format selects fp32 world

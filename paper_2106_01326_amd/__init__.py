@@ -48,7 +48,7 @@ EXPORTED = ("tv_grid_words", "tv_workspace_bytes", "tv_voxelize", "tv_voxelize_q
             "tv_server_release", "tv_server_get_stats", "tv_server_destroy", "tv_unpack", "tv_pool",
             "tv_brick_count_max", "tv_bricks_workspace_bytes", "tv_bricks", "tv_read_mesh",
             "tv_free_host_mesh", "tv_quality_workspace_bytes", "tv_mesh_quality",
-            "tv_voxelize_pipelined")
+            "tv_voxelize_pipelined", "tv_voxelize_noalloc")
 
 UNPACK_U8 = 0
 UNPACK_F32 = 1
@@ -163,6 +163,8 @@ def load_library():
     lib.tv_voxelize.restype = st
     lib.tv_voxelize_q.argtypes = [P, i64, P, i64, Dims, P, P, ctypes.c_size_t, P, u32]
     lib.tv_voxelize_q.restype = st
+    lib.tv_voxelize_noalloc.argtypes = [P, i64, P, i64, Dims, BBox, P, P, P, u32]
+    lib.tv_voxelize_noalloc.restype = st
     lib.tv_batch_workspace_bytes.argtypes = [P, ctypes.c_int32, u32]
     lib.tv_batch_workspace_bytes.restype = ctypes.c_size_t
     lib.tv_voxelize_batch.argtypes = [P, ctypes.c_int32, P, ctypes.c_size_t, P, u32]
@@ -340,6 +342,34 @@ def voxelize(verts, tets, dims, bbox=None, *, qverts=False, strict=False, per_te
         rc = lib.tv_voxelize(vptr, nv, tptr, nt, d, _bbox(bbox), gptr, wptr, workspace.numel(), s, flags)
     _check(rc)
     return grid, workspace
+
+
+NOALLOC_MAX_BYTES = 64 << 20  # TV_NOALLOC_MAX_BYTES
+
+
+def voxelize_noalloc(verts, tets, dims, bbox, *, strict=False, grid=None, status=None, stream=None):
+    """Voxelize one mesh (fp32 world coordinates) with the library's fixed
+    per-GPU scratch array instead of a workspace (tv_voxelize_noalloc).
+    ``grid`` and ``status`` (a one-element int32 device tensor receiving the
+    data-error status) are allocated here when not given; pass them to keep
+    the call free of allocations.  Returns (grid, status)."""
+    lib = load_library()
+    torch = _torch()
+    d = _dims(dims)
+    vptr, nv = _dev_ptr(verts, torch.float32, 3, "verts")
+    tptr, nt = _dev_ptr(tets, torch.int32, 4, "tets")
+    if grid is None:
+        grid = alloc_grid(dims, verts.device)
+    gptr, _ = _dev_ptr(grid, torch.int32, None, "grid")
+    if grid.numel() < grid_words(dims):
+        raise ValueError("grid tensor too small")
+    if status is None:
+        status = torch.empty(1, dtype=torch.int32, device=verts.device)
+    sptr, _ = _dev_ptr(status, torch.int32, None, "status")
+    rc = lib.tv_voxelize_noalloc(vptr, nv, tptr, nt, d, _bbox(bbox), gptr, sptr, _stream_handle(stream),
+                                 TIE_STRICT if strict else TIE_HALF_OPEN)
+    _check(rc)
+    return grid, status
 
 
 def voxelize_pipelined(verts_host, tets_host, dims, bbox, chunks=8, *, strict=False, per_tet=False,

@@ -193,9 +193,10 @@ tv::MeshTable make_table(const tv::CallSizes &c, uint8_t *ws, const tv::MeshDesc
 }
 
 // The launch sequence: kernels only (no host copies, memsets or
-// allocations).  `descs` is needed by the per-tet reference path only.
+// allocations).  The host descriptors `descs[0, ndescs)` are needed by the
+// per-tet reference path only.
 tv_status enqueue(const tv::MeshTable &T, const tv::CallSizes &c, uint8_t *ws, hipStream_t s,
-                  uint32_t flags, const std::vector<tv::MeshDesc> *descs, int wgs_per_cu) {
+                  uint32_t flags, const tv::MeshDesc *descs, size_t ndescs, int wgs_per_cu) {
     const tv::WorkspaceLayout L = tv::layout(c);
     const tv::BinBuffers b = tv::bin_buffers(ws, L);
     const bool strict = (flags & TV_TIE_STRICT) != 0;
@@ -221,7 +222,8 @@ tv_status enqueue(const tv::MeshTable &T, const tv::CallSizes &c, uint8_t *ws, h
     if (flags & TV_PATH_PER_TET) {
         if (!descs) return fail(TV_ERR_INVALID_ARG, "the per-tet path needs host descriptors");
         tv::StageScope sc(tv::kStageVoxelize, s);
-        for (const tv::MeshDesc &d : *descs) {
+        for (size_t i = 0; i < ndescs; ++i) {
+            const tv::MeshDesc &d = descs[i];
             if (!accumulate) tv::launch_clear(d.grid, (int64_t)d.g.n[0] * d.g.n[1] * d.g.words, s);
             tv::launch_voxelize_per_tet(d, b, strict, s);
         }
@@ -256,7 +258,7 @@ tv_status run_impl(std::vector<tv::MeshDesc> &descs, const tv::CallSizes &c, uin
         if (st) return st;
     }
     const tv::MeshTable T = make_table(c, ws, descs.data(), flags, P);
-    return enqueue(T, c, ws, s, flags, &descs, P.wgs_per_cu);
+    return enqueue(T, c, ws, s, flags, descs.data(), descs.size(), P.wgs_per_cu);
 }
 
 // Workspace bytes of a single-mesh call under parameters P.
@@ -356,6 +358,49 @@ tv_status set_error(tv_status code, const char *fmt, ...) {
 }
 
 }  // namespace tv
+
+// ------------------------------------------------ allocation-free call
+//
+// tv_voxelize_noalloc takes its workspace from a fixed device array instead
+// of the caller.  Host code must never pass `scratch` itself to a kernel or a
+// copy: in host code the name is only a stand-in for the symbol, so the
+// device address of each GPU's copy is fetched once per device with
+// hipGetSymbolAddress and cached.
+constexpr size_t kStaticScratchBytes = TV_NOALLOC_MAX_BYTES;
+static __device__ __align__(256) uint8_t scratch[kStaticScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint8_t *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch array.
+tv_status static_scratch(uint8_t **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(TV_ERR_HIP, "hipGetDevice failed");
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(TV_ERR_HIP, "device %d beyond the %d the scratch table holds", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(TV_ERR_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                        hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<uint8_t *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return TV_OK;
+}
+
+// The call's data-error status word -> a tv_status, in device memory.
+__global__ void k_status_code(const uint32_t *word, int32_t *out) {
+    const uint32_t w = *word;
+    *out = (w & tv::kStatusIndex) ? TV_ERR_INDEX : (w & tv::kStatusRange) ? TV_ERR_RANGE : TV_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -503,7 +548,7 @@ tv_status tv_batch_run(const tv_batch_plan *plan, void *ws, size_t ws_bytes, voi
     P.wgs_per_cu = plan->launch[3];
     P.cull = plan->launch[4];
     const tv::MeshTable T = make_table(c, w, nullptr, plan->flags, P);
-    return enqueue(T, c, w, reinterpret_cast<hipStream_t>(stream), plan->flags, nullptr,
+    return enqueue(T, c, w, reinterpret_cast<hipStream_t>(stream), plan->flags, nullptr, 0,
                    P.wgs_per_cu);
 }
 
@@ -625,5 +670,37 @@ const char *tv_status_string(tv_status s) {
 }
 
 const char *tv_last_error(void) { return g_last_error; }
+
+tv_status tv_voxelize_noalloc(const float *verts, int64_t nv, const int32_t *tets, int64_t nt,
+                              tv_dims dims, tv_bbox bbox, uint32_t *grid, int32_t *status_out,
+                              void *stream, uint32_t flags) {
+    tv_status st = check_mesh_impl(verts, TV_VERTS_F32, nv, tets, nt, dims, &bbox, grid, "");
+    if (st) return st;
+    if (flags & ~(uint32_t)TV_TIE_STRICT)
+        return fail(TV_ERR_INVALID_ARG, "tv_voxelize_noalloc takes TV_TIE_STRICT only (flags 0x%x)",
+                    flags);
+    const tv::Params P = current_params(0);
+    const size_t need = single_ws_bytes(nv, nt, dims, P);
+    if (need > kStaticScratchBytes)
+        return fail(TV_ERR_WORKSPACE,
+                    "mesh needs %zu bytes of scratch; the allocation-free call holds %zu "
+                    "(use tv_voxelize with a workspace)",
+                    need, kStaticScratchBytes);
+    uint8_t *ws = nullptr;
+    if ((st = static_scratch(&ws))) return st;
+    const tv::MeshDesc d = make_desc_impl(verts, TV_VERTS_F32, nv, tets, nt, dims, &bbox, grid, P);
+    tv::MeshDesc one = d;
+    one.mesh = 0;
+    const tv::CallSizes c = {1, nv, nt, d.p.ntiles, false};
+    const tv::MeshTable T = make_table(c, ws, &one, flags, P);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if ((st = enqueue(T, c, ws, s, flags, &one, 1, P.wgs_per_cu))) return st;
+    if (status_out) {
+        const tv::WorkspaceLayout L = tv::layout(c);
+        k_status_code<<<1, 1, 0, s>>>(reinterpret_cast<const uint32_t *>(ws + L.status), status_out);
+        return check_hip("status launch");
+    }
+    return TV_OK;
+}
 
 }  // extern "C"

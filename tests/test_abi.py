@@ -169,3 +169,29 @@ def test_tune_cache_roundtrip(tmp_path):
         tv.set_params("batch", None)
     assert tune.size_class_single(5_557_093, (1024, 1024, 1024)) == "nt2^22:dims1024x1024x1024"
     assert tune.size_class_batch(1024, 42_800_000) == "n2^10:nt2^25"
+
+
+def test_noalloc_host_checks(lib):
+    """tv_voxelize_noalloc refuses what the host can see before touching the
+    device: sizes beyond its fixed scratch array and flags it does not take."""
+    import re
+
+    from helpers import ROOT
+
+    text = open(os.path.join(ROOT, "include", "tv.h")).read()
+    m = re.search(r"#define TV_NOALLOC_MAX_BYTES \(\(size_t\)(\d+) << (\d+)\)", text)
+    assert m and int(m.group(1)) << int(m.group(2)) == tv.NOALLOC_MAX_BYTES
+    P = ctypes.c_void_p
+    d = tv.Dims(32, 32, 32)
+    box = tv._bbox(((0, 0, 0), (1, 1, 1)))
+    big = tv.NOALLOC_MAX_BYTES // 40
+    assert tv.workspace_bytes(4, big, (32, 32, 32)) > tv.NOALLOC_MAX_BYTES
+    call = lib.tv_voxelize_noalloc
+    assert call(P(256), 4, P(256), big, d, box, P(256), None, None, 0) == tv.TV_ERR_WORKSPACE
+    assert call(P(256), 4, P(256), 1, d, box, P(256), None, None, tv.ACCUMULATE) == tv.TV_ERR_INVALID_ARG
+    assert call(P(256), 4, P(256), 1, d, box, P(256), None, None, tv.PATH_PER_TET) == tv.TV_ERR_INVALID_ARG
+    assert call(P(256), 4, P(256), 1, d, box, None, None, None, 0) == tv.TV_ERR_INVALID_ARG
+    assert call(P(256), 4, P(256), 1, tv.Dims(32, 24, 32), box, P(256), None, None, 0) == \
+        tv.TV_ERR_UNSUPPORTED_DIMS
+    bad = tv._bbox(((0, 0, 0), (1, 0, 1)))
+    assert call(P(256), 4, P(256), 1, d, bad, P(256), None, None, 0) == tv.TV_ERR_INVALID_ARG
