@@ -504,9 +504,11 @@ __device__ __forceinline__ int4 load_int4(gptr<int4> base, int64_t i) {
 
 // ------------------------------------------------------ tile voxelization
 
-constexpr int kTileThreads = 256;
-constexpr int kMaxTileWords = 4096;  // 16 KiB of LDS bitmap
-constexpr int kRowPool = 4096;       // per-batch row entries (16 KiB)
+constexpr int kTileThreads = 256;                 // four waves
+constexpr int kTileWaves = kTileThreads / 64;
+constexpr int kMaxTileWords = 4096;               // 16 KiB of LDS bitmap
+constexpr int kWaveBatch = 64;                    // pieces per wave batch (one per lane)
+constexpr int kRowPool = 1024;                    // row entries per wave batch (4 KiB)
 
 struct PieceRec {
     Face f[4];
@@ -591,52 +593,60 @@ __device__ __forceinline__ void row_columns(const RowHull &h, double cx, const G
     j1 = (int32_t)floor((yhi + 1.0 - S) * inv);
 }
 
-// Exclusive scan of v[0..255] in place by the first wave (4 values per lane);
-// writes the total to v[256].  With `first_over`, also stores the index of
-// the first entry whose end (offset + value) exceeds `cap` (256 if none).
-__device__ __forceinline__ void scan256_wave0(uint32_t *v, int tid, uint32_t *first_over,
-                                              uint32_t cap) {
-    if (tid < 64) {
-        const uint32_t v0 = v[4 * tid], v1 = v[4 * tid + 1], v2 = v[4 * tid + 2],
-                       v3 = v[4 * tid + 3];
-        const uint32_t sum = v0 + v1 + v2 + v3;
-        uint32_t incl = sum;
-        for (int off = 1; off < 64; off <<= 1) {
-            const uint32_t o = __shfl_up(incl, off);
-            if (tid >= off) incl += o;
-        }
-        const uint32_t ex = incl - sum;
-        const uint32_t e[4] = {ex, ex + v0, ex + v0 + v1, ex + v0 + v1 + v2};
-        const uint32_t w[4] = {v0, v1, v2, v3};
-        uint32_t first = kTileThreads;
+// Wave-level scans (one value per lane of a 64-lane wave).
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            v[4 * tid + q] = e[q];
-            if (e[q] + w[q] > cap) first = min(first, (uint32_t)(4 * tid + q));
-        }
-        if (first_over) {
-            for (int off = 32; off > 0; off >>= 1)
-                first = min(first, (uint32_t)__shfl_xor((int)first, off));
-            if (tid == 0) *first_over = first;
-        }
-        if (tid == 63) v[kTileThreads] = incl;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t o = __shfl_up(v, off);
+        if (lane >= off) v += o;
     }
+    return v;
 }
 
+// Next range of pieces for a wave: lane 0 advances the chunk's LDS cursor,
+// every lane gets the start.
+__device__ __forceinline__ uint32_t grab_pieces(uint32_t *cursor, int lane) {
+    uint32_t v = 0;
+    if (lane == 0) v = atomicAdd(cursor, (uint32_t)kWaveBatch);
+    return __shfl(v, 0);
+}
+
+// Saturating double -> int32 conversion (the hardware conversion clamps to
+// [INT32_MIN, INT32_MAX]); used on integral values only.
+__device__ __forceinline__ int32_t cvt_sat_i32(double x) {
+    int32_t r;
+    asm("v_cvt_i32_f64 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
+// The tile kernel.  Persistent workgroups take tasks (chunks of one tile's
+// pieces) from the queue, largest tiles first.  Inside a task the four waves
+// work independently: each takes batches of up to 64 pieces from the task
+// and runs, without workgroup barriers,
+//   (1a) one lane per piece: clipped box and the four faces -> LDS record
+//        (the next batch's tets and vertices are already loading);
+//   (1c) one lane per piece: the rows of the tet's xy projection, only
+//        non-empty rows kept, into the wave's row pool;
+//   (3)  the batch's kept columns cut into strips; each lane walks a
+//        contiguous block of strips, decides each column's span exactly and
+//        ORs it into the tile bitmap (LDS atomics, shared by the waves).
+// The tile is written out once, after the last wave is done.
 __global__ void __launch_bounds__(kTileThreads)
     k_tile_voxelize(MeshTable T, BinBuffers b, int strict) {
     __shared__ uint32_t s_bits[kMaxTileWords];
-    __shared__ PieceRec s_rec[kTileThreads];
+    __shared__ PieceRec s_rec[kTileWaves][kWaveBatch];
     // non-empty rows: j0 (8 bits) | count (8 bits) | di (6 bits) | prefix (10 bits)
-    __shared__ uint32_t s_row[kRowPool];
-    __shared__ uint32_t s_soff[kTileThreads + 1];
-    __shared__ uint32_t s_roff[kTileThreads + 1];
-    __shared__ uint32_t s_chunk, s_tile, s_p0, s_p1, s_shared, s_nb;
+    __shared__ uint32_t s_row[kTileWaves][kRowPool];
+    __shared__ uint32_t s_soff[kTileWaves][kWaveBatch + 1];
+    __shared__ uint32_t s_chunk, s_tile, s_p0, s_p1, s_shared, s_next;
     __shared__ int32_t s_mesh;
 
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const uint32_t strip = (uint32_t)T.strip;
     const uint32_t total = b.meta[kMetaChunks];
+    PieceRec *const rec = s_rec[wv];
+    uint32_t *const rows = s_row[wv];
+    uint32_t *const soff = s_soff[wv];
 
     for (;;) {
         if (tid == 0) {
@@ -657,6 +667,7 @@ __global__ void __launch_bounds__(kTileThreads)
                 s_tile = tile;
                 s_p0 = min(pe, pb + k * (uint32_t)T.chunk);
                 s_p1 = min(pe, pb + (k + 1) * (uint32_t)T.chunk);
+                s_next = s_p0;
                 s_shared = nchunks > 1 ? 1u : 0u;
                 s_mesh = T.n == 1 ? 0 : find_mesh(T.tile_pre, T.n, (int64_t)tile);
             }
@@ -679,25 +690,28 @@ __global__ void __launch_bounds__(kTileThreads)
         const int32_t ti0 = o.i0, tj0 = o.j0, tk0 = o.k0;
         const int32_t ti1 = ti0 + (1 << p.lx) - 1, tj1 = tj0 + (1 << p.ly) - 1;
         const int32_t tk1 = min(tk0 + (tw << 5) - 1, g.n[2] - 1);
+        __syncthreads();  // bitmap cleared, s_next set
 
-        uint32_t pb = s_p0;
+        // this wave's pending pieces: [pb, rend)
+        uint32_t pb = grab_pieces(&s_next, lane);
+        uint32_t rend = min(pb + (uint32_t)kWaveBatch, p1);
         // vertex records of this lane's piece in the next batch; loaded ahead
         // (the piece id -> tet -> vertex chain is three dependent gathers)
         int4 Vn[4];
-        if (pb + tid < p1) {
-            const int4 Tt = load_int4(tets, pieces[pb + tid] - tbase);
+        if (pb + lane < rend) {
+            const int4 Tt = load_int4(tets, pieces[pb + lane] - tbase);
             Vn[0] = load_int4(q4, Tt.x);
             Vn[1] = load_int4(q4, Tt.y);
             Vn[2] = load_int4(q4, Tt.z);
             Vn[3] = load_int4(q4, Tt.w);
         }
-        while (pb < p1) {
+        while (pb < rend) {
             // phase 1a: one lane per piece: clipped box, faces -> record
-            const uint32_t pi = pb + tid;
+            const uint32_t pi = pb + lane;
             int32_t lo[3] = {0, 0, 0}, hi[3] = {-1, -1, -1};
             int4 Vt[4];
             uint32_t nrows = 0;
-            if (pi < p1) {
+            if (pi < rend) {
                 const int4 A = Vn[0], B = Vn[1], C = Vn[2], D = Vn[3];
                 Vt[0] = A;
                 Vt[1] = B;
@@ -717,12 +731,11 @@ __global__ void __launch_bounds__(kTileThreads)
                     Face f[4];
                     uint32_t lower;
                     if (build_faces(A, B, C, D, p0d, g, strict != 0, f, lower)) {
-                        PieceRec &R = s_rec[tid];
+                        PieceRec &R = rec[lane];
 #pragma unroll
                         for (int fi = 0; fi < 4; ++fi) R.f[fi] = f[fi];
                         R.ci0 = (int16_t)(lo[0] - ti0);
                         R.cj0 = (int16_t)(lo[1] - tj0);
-                        R.ni = (int16_t)(hi[0] - lo[0] + 1);
                         R.k0 = (int16_t)(lo[2] - tk0);
                         R.nk = (int16_t)(hi[2] - lo[2] + 1);
                         R.lower = (uint16_t)lower;
@@ -733,27 +746,30 @@ __global__ void __launch_bounds__(kTileThreads)
             // phase 1b: row-pool offsets; the batch ends before the first
             // piece whose rows no longer fit (a piece has at most 32 rows, so
             // every batch makes progress)
-            s_roff[tid] = nrows;
-            __syncthreads();
-            scan256_wave0(s_roff, tid, &s_nb, (uint32_t)kRowPool);
-            __syncthreads();
-            const uint32_t nb = min(s_nb, p1 - pb);
+            const uint32_t rincl = wave_incl_scan(nrows, lane);
+            const uint32_t nb = min((uint32_t)__popcll(__ballot(rincl <= (uint32_t)kRowPool)), rend - pb);
+            // the next batch: the rest of this range, or a new one
+            uint32_t nbeg = pb + nb, nend = rend;
+            if (nbeg >= rend) {
+                nbeg = grab_pieces(&s_next, lane);
+                nend = min(nbeg + (uint32_t)kWaveBatch, p1);
+            }
             // the next batch's tet record, then (after phase 1c) its vertices
             // (unconditional, with the index clamped to this chunk's last piece,
             // so that nothing waits for it before its use)
-            const uint32_t pn = pb + nb + tid;
+            const uint32_t pn = nbeg + lane;
             int4 Tn = load_int4(tets, pieces[min(pn, p1 - 1)] - tbase);
             // phase 1c: per-row column ranges of the pieces in this batch
             uint32_t nstrips = 0;
-            if ((uint32_t)tid < nb && nrows) {
-                PieceRec &R = s_rec[tid];
-                const uint32_t base = s_roff[tid];
+            if ((uint32_t)lane < nb && nrows) {
+                PieceRec &R = rec[lane];
+                const uint32_t base = rincl - nrows;
                 uint32_t prefix = 0, kept = 0;
                 const uint32_t bw = (uint32_t)(hi[1] - lo[1] + 1);
                 if (nrows * bw <= (uint32_t)T.nocull) {
                     // a box this small loses too little to culling to pay for it
                     for (uint32_t rr = 0; rr < nrows; ++rr) {
-                        s_row[base + rr] = (bw << 8) | (rr << 16) | (prefix << 22);
+                        rows[base + rr] = (bw << 8) | (rr << 16) | (prefix << 22);
                         prefix += bw;
                     }
                     kept = nrows;
@@ -768,7 +784,7 @@ __global__ void __launch_bounds__(kTileThreads)
                         j1 = min(j1, hi[1]);
                         if (j1 >= j0) {
                             const uint32_t cnt = (uint32_t)(j1 - j0 + 1);
-                            s_row[base + kept] =
+                            rows[base + kept] =
                                 (uint32_t)(j0 - lo[1]) | (cnt << 8) | (rr << 16) | (prefix << 22);
                             ++kept;
                             prefix += cnt;
@@ -782,35 +798,33 @@ __global__ void __launch_bounds__(kTileThreads)
             }
             // keeps the use of the tet record (and so its wait) after phase 1c
             asm volatile("" : "+v"(Tn.x), "+v"(Tn.y), "+v"(Tn.z), "+v"(Tn.w));
-            if (pn < p1) {
+            if (pn < nend) {
                 Vn[0] = load_int4(q4, Tn.x);
                 Vn[1] = load_int4(q4, Tn.y);
                 Vn[2] = load_int4(q4, Tn.z);
                 Vn[3] = load_int4(q4, Tn.w);
             }
             // phase 2: exclusive scan of strip counts
-            s_soff[tid] = nstrips;
-            __syncthreads();
-            scan256_wave0(s_soff, tid, nullptr, 0xffffffffu);
-            __syncthreads();
+            const uint32_t sincl = wave_incl_scan(nstrips, lane);
+            if (lane < kWaveBatch) soff[lane] = sincl - nstrips;
+            const uint32_t nst = __shfl(sincl, 63);
+            if (lane == 63) soff[kWaveBatch] = nst;
             // phase 3: the batch's kept columns in strips of `strip`; each lane
             // takes a contiguous block of strips, so its faces and its row
             // position carry over from one strip to the next of the same piece
-            const uint32_t nst = s_soff[kTileThreads];
-            const uint32_t sb = (uint32_t)(((uint64_t)nst * (uint32_t)tid) / kTileThreads);
-            const uint32_t se = (uint32_t)(((uint64_t)nst * (uint32_t)(tid + 1)) / kTileThreads);
+            const uint32_t sb = (uint32_t)(((uint64_t)nst * (uint32_t)lane) >> 6);
+            const uint32_t se = (uint32_t)(((uint64_t)nst * (uint32_t)(lane + 1)) >> 6);
             if (sb < se) {
-                int32_t pc = 0, hi_r = kTileThreads;  // s_soff[pc] <= sb < s_soff[hi_r]
+                int32_t pc = 0, hi_r = kWaveBatch;  // soff[pc] <= sb < soff[hi_r]
                 while (hi_r - pc > 1) {
                     const int32_t mid = (pc + hi_r) >> 1;
-                    if (s_soff[mid] <= sb) pc = mid;
+                    if (soff[mid] <= sb) pc = mid;
                     else hi_r = mid;
                 }
-                Face f[4];
-                int32_t mlo[4];  // -1 for a face that starts the span, 0 for one that ends it
-                int32_t nk = 0, k0 = 0, ci0 = 0, cj0 = 0, di = 0, dj = 0, jend = 0;
+                double fA[4], fX[4], fY[4], fS[4], fR[4];
+                int32_t ml[4], nml[4], nkm[4];  // per face: lower mask, its complement, nk & mask
+                int32_t k0 = 0, colb = 0, di = 0, dj = 0, jend = 0;
                 uint32_t ncols = 0, pfirst = 0, pend = 0, r = 0;
-                double nkd = 0.0;
                 bool first = true;
                 for (uint32_t s = sb; s < se; ++s) {
                     if (first || s == pend) {
@@ -818,33 +832,37 @@ __global__ void __launch_bounds__(kTileThreads)
                         // column in this lane's block
                         if (!first)
                             do ++pc;
-                            while (s_soff[pc + 1] <= s);
+                            while (soff[pc + 1] <= s);
                         first = false;
-                        const PieceRec &R = s_rec[pc];
+                        const PieceRec &R = rec[pc];
+                        const int32_t nk = R.nk;
 #pragma unroll
                         for (int fi = 0; fi < 4; ++fi) {
-                            f[fi] = R.f[fi];
-                            mlo[fi] = ((R.lower >> fi) & 1u) ? -1 : 0;
+                            fA[fi] = R.f[fi].A;
+                            fX[fi] = R.f[fi].SX;
+                            fY[fi] = R.f[fi].SY;
+                            fS[fi] = R.f[fi].S;
+                            fR[fi] = (double)R.f[fi].R;
+                            ml[fi] = -(int32_t)((R.lower >> fi) & 1u);
+                            nml[fi] = ~ml[fi];
+                            nkm[fi] = nk & ml[fi];
                         }
-                        nk = R.nk;
                         k0 = R.k0;
-                        ci0 = R.ci0;
-                        cj0 = R.cj0;
+                        colb = ((int32_t)R.ci0 << p.ly) + R.cj0;
                         ncols = R.ncols;
-                        nkd = (double)nk;
-                        pfirst = s_soff[pc];
-                        pend = s_soff[pc + 1];
+                        pfirst = soff[pc];
+                        pend = soff[pc + 1];
                         const uint32_t row0 = R.row0;
                         const uint32_t cs = (s - pfirst) * strip;
                         // row entry holding kept column cs: last entry with prefix <= cs
                         uint32_t ra = 0, rb = cs ? (uint32_t)R.ni : 1u;
                         while (rb - ra > 1) {
                             const uint32_t mid = (ra + rb) >> 1;
-                            if ((s_row[row0 + mid] >> 22) <= cs) ra = mid;
+                            if ((rows[row0 + mid] >> 22) <= cs) ra = mid;
                             else rb = mid;
                         }
                         r = row0 + ra;
-                        const uint32_t rw = s_row[r];
+                        const uint32_t rw = rows[r];
                         di = (int32_t)((rw >> 16) & 63u);
                         dj = (int32_t)(rw & 0xffu) + (int32_t)(cs - (rw >> 22));
                         jend = (int32_t)(rw & 0xffu) + (int32_t)((rw >> 8) & 0xffu);
@@ -854,20 +872,30 @@ __global__ void __launch_bounds__(kTileThreads)
                     for (uint32_t c = c0; c < c1; ++c) {
                         // the next row entry, read one column ahead (used only on a
                         // row change, which happens only while columns remain)
-                        const uint32_t nx = s_row[min(r + 1, (uint32_t)kRowPool - 1)];
+                        const uint32_t nx = rows[min(r + 1, (uint32_t)kRowPool - 1)];
                         const double ddi = (double)di, ddj = (double)dj;
                         int32_t tl[4], tu[4];
 #pragma unroll
                         for (int fi = 0; fi < 4; ++fi) {
-                            const double a = fma(f[fi].SY, ddj, fma(f[fi].SX, ddi, f[fi].A));
-                            const int32_t t = face_threshold(f[fi], a, nkd);  // in [0, nk + 1]
-                            tl[fi] = t & mlo[fi];                              // 0: no lower bound
-                            tu[fi] = (t & ~mlo[fi]) | (nk & mlo[fi]);          // nk: no upper bound
+                            // threshold: first dk with a + S dk >= 0 (see
+                            // face_threshold), here without the clamp to
+                            // [0, nk]: the estimate is capped at 2^30 so that
+                            // the +1 cannot overflow, and the conversion
+                            // saturates below.  A value below 0 or above nk
+                            // acts as 0 or nk in the max / min that follow,
+                            // since every tet has a lower face (which gives
+                            // nk in the upper list) and an upper face (0 in
+                            // the lower list).
+                            const double a = fma(fY[fi], ddj, fma(fX[fi], ddi, fA[fi]));
+                            const double e = fmin(ceil(fma(-a, fR[fi], -0.5)), 1073741824.0);
+                            const int32_t t = cvt_sat_i32(e) + (fma(fS[fi], e, a) < 0.0 ? 1 : 0);
+                            tl[fi] = t & ml[fi];
+                            tu[fi] = (t & nml[fi]) | nkm[fi];
                         }
                         const int32_t zlo = max(max(tl[0], tl[1]), max(tl[2], tl[3]));
-                        const int32_t zhi = min(min(tu[0], tu[1]), min(min(tu[2], tu[3]), nk));
+                        const int32_t zhi = min(min(tu[0], tu[1]), min(tu[2], tu[3]));
                         if (zlo < zhi)
-                            or_run_lds(s_bits + (((ci0 + di) << p.ly) + cj0 + dj) * tw, k0 + zlo,
+                            or_run_lds(s_bits + ((colb + (di << p.ly) + dj) << p.lw), k0 + zlo,
                                        k0 + zhi);
                         // advance along the row, or to the next non-empty row
                         const bool wrap = ++dj == jend;
@@ -879,9 +907,10 @@ __global__ void __launch_bounds__(kTileThreads)
                     }
                 }
             }
-            __syncthreads();
-            pb += nb;
+            pb = nbeg;
+            rend = nend;
         }
+        __syncthreads();  // every wave done with this task's bitmap
 
         // flush the tile: word x of the bitmap is word (x & (tw-1)) of
         // tile-local column x >> lw
@@ -889,16 +918,16 @@ __global__ void __launch_bounds__(kTileThreads)
         const int64_t zbase = tk0 >> 5;
         uint32_t *__restrict__ grid = d.grid;
         for (int32_t x = tid; x < nwords; x += kTileThreads) {
-            const uint32_t wv = s_bits[x];
+            const uint32_t wv_ = s_bits[x];
             const int32_t cl = x >> p.lw;
             const int64_t i = ti0 + (cl >> p.ly), j = tj0 + (cl & ((1 << p.ly) - 1));
             const int64_t gw = (i * g.n[1] + j) * g.words + zbase + (x & (tw - 1));
             if (shared_tile) {
-                if (wv) __hip_atomic_fetch_or(grid + gw, wv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (wv_) __hip_atomic_fetch_or(grid + gw, wv_, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             } else if (!T.accumulate) {
-                grid[gw] = wv;
-            } else if (wv) {
-                grid[gw] |= wv;  // this chunk owns the tile within the call
+                grid[gw] = wv_;
+            } else if (wv_) {
+                grid[gw] |= wv_;  // this chunk owns the tile within the call
             }
         }
         __syncthreads();
