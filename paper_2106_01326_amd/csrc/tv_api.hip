@@ -116,6 +116,7 @@ tv::MeshDesc make_desc_impl(const void *verts, uint32_t fmt, int64_t nv, const i
     d.g = make_geom(dims);
     d.p = tv::plan_tiles(dims, P.min_tiles, P.tile_cols_log2);
     d.fmt = fmt == TV_VERTS_F32 ? tv::kFmtF32 : tv::kFmtQ32;
+    d.direct = d.p.ntiles == 1 ? 1 : 0;
     if (fmt == TV_VERTS_F32) {
         for (int a = 0; a < 3; ++a) {
             d.box.lo[a] = (double)bbox->lo[a];

@@ -39,6 +39,8 @@ struct MeshDesc {
     TilePlan p;
     int32_t fmt;         // kFmtF32 / kFmtQ32
     int32_t mesh;        // index (status word)
+    int32_t direct;      // the grid is a single tile: its pieces are the mesh's tets in
+                         // order, never binned (the tile kernel checks their indices)
 };
 
 // The meshes of one call.  A single mesh travels by value in `one`; a batch

@@ -277,7 +277,11 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(MeshTable T, BinBuffers b) 
     auto tile_summary = [&](int u, int64_t t, const MeshDesc &d) {
         sys[u] = (uint32_t)d.p.ntz;
         sxs[u] = (uint32_t)d.p.nty * sys[u];
-        if (!kScatter) {
+        if (d.direct) {
+            // a single-tile grid: every tet is a piece of tile 0, in tet
+            // order, so the count is the tet count and nothing is scattered
+            if (!kScatter && t == d.tet_base) b.tile_count[d.tile_base] = (uint32_t)d.nt;
+        } else if (!kScatter) {
             TileRange r = {0, -1, 0, -1, 0, -1};
             int32_t n = tet_pieces(d, b.q4, t - d.tet_base, b.status, r);
             if (n > T.piece_cap) {
@@ -638,7 +642,7 @@ __global__ void __launch_bounds__(kTileThreads)
     // non-empty rows: j0 (8 bits) | count (8 bits) | di (6 bits) | prefix (10 bits)
     __shared__ uint32_t s_row[kTileWaves][kRowPool];
     __shared__ uint32_t s_soff[kTileWaves][kWaveBatch + 1];
-    __shared__ uint32_t s_chunk, s_tile, s_p0, s_p1, s_shared, s_next;
+    __shared__ uint32_t s_chunk, s_tile, s_p0, s_p1, s_shared, s_next, s_pbase;
     __shared__ int32_t s_mesh;
 
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -668,6 +672,7 @@ __global__ void __launch_bounds__(kTileThreads)
                 s_p0 = min(pe, pb + k * (uint32_t)T.chunk);
                 s_p1 = min(pe, pb + (k + 1) * (uint32_t)T.chunk);
                 s_next = s_p0;
+                s_pbase = pb;
                 s_shared = nchunks > 1 ? 1u : 0u;
                 s_mesh = T.n == 1 ? 0 : find_mesh(T.tile_pre, T.n, (int64_t)tile);
             }
@@ -682,6 +687,13 @@ __global__ void __launch_bounds__(kTileThreads)
         const gptr<int4> tets = as_global(d.tets);
         const gptr<uint32_t> pieces = as_global(b.pieces);
         const uint32_t tbase = (uint32_t)d.tet_base;
+        // the mesh-local tet of piece slot x: binned pieces hold global tet
+        // ids; a single-tile grid's pieces are its tets in order (unbinned,
+        // so their indices are checked here)
+        const bool direct = d.direct != 0;
+        const uint32_t pbase = s_pbase;
+        const int64_t nv = d.nv;
+        auto tet_of = [&](uint32_t x) -> uint32_t { return direct ? x - pbase : pieces[x] - tbase; };
         const int32_t tw = 1 << p.lw;
         const int32_t nwords = (1 << (p.lx + p.ly)) * tw;
         for (int32_t x = tid; x < nwords; x += kTileThreads) s_bits[x] = 0u;
@@ -698,8 +710,11 @@ __global__ void __launch_bounds__(kTileThreads)
         // vertex records of this lane's piece in the next batch; loaded ahead
         // (the piece id -> tet -> vertex chain is three dependent gathers)
         int4 Vn[4];
+        bool idx_ok = true;  // the prefetched tet's indices are in range
         if (pb + lane < rend) {
-            const int4 Tt = load_int4(tets, pieces[pb + lane] - tbase);
+            int4 Tt = load_int4(tets, tet_of(pb + lane));
+            idx_ok = index_ok(Tt.x, nv) && index_ok(Tt.y, nv) && index_ok(Tt.z, nv) && index_ok(Tt.w, nv);
+            if (!idx_ok) Tt = make_int4(0, 0, 0, 0);
             Vn[0] = load_int4(q4, Tt.x);
             Vn[1] = load_int4(q4, Tt.y);
             Vn[2] = load_int4(q4, Tt.z);
@@ -711,7 +726,10 @@ __global__ void __launch_bounds__(kTileThreads)
             int32_t lo[3] = {0, 0, 0}, hi[3] = {-1, -1, -1};
             int4 Vt[4];
             uint32_t nrows = 0;
-            if (pi < rend) {
+            if (pi < rend && !idx_ok) atomicOr(b.status + d.mesh, kStatusIndex);
+            // a vertex that failed ingest voids its tets (its mesh's status
+            // was raised there)
+            if (pi < rend && idx_ok && (Vn[0].w | Vn[1].w | Vn[2].w | Vn[3].w) == 0) {
                 const int4 A = Vn[0], B = Vn[1], C = Vn[2], D = Vn[3];
                 Vt[0] = A;
                 Vt[1] = B;
@@ -732,8 +750,18 @@ __global__ void __launch_bounds__(kTileThreads)
                     uint32_t lower;
                     if (build_faces(A, B, C, D, p0d, g, strict != 0, f, lower)) {
                         PieceRec &R = rec[lane];
+                        // faces stored lower ones first: slot 0 always starts
+                        // the span and slot 3 always ends it (every tet has both)
+                        const uint32_t nl = __popc(lower);
 #pragma unroll
-                        for (int fi = 0; fi < 4; ++fi) R.f[fi] = f[fi];
+                        for (int fi = 0; fi < 4; ++fi) {
+                            const uint32_t below = (1u << fi) - 1u;
+                            const uint32_t slot = ((lower >> fi) & 1u)
+                                                      ? __popc(lower & below)
+                                                      : nl + __popc(~lower & below);
+                            R.f[slot] = f[fi];
+                        }
+                        lower = (1u << nl) - 1u;
                         R.ci0 = (int16_t)(lo[0] - ti0);
                         R.cj0 = (int16_t)(lo[1] - tj0);
                         R.k0 = (int16_t)(lo[2] - tk0);
@@ -758,7 +786,7 @@ __global__ void __launch_bounds__(kTileThreads)
             // (unconditional, with the index clamped to this chunk's last piece,
             // so that nothing waits for it before its use)
             const uint32_t pn = nbeg + lane;
-            int4 Tn = load_int4(tets, pieces[min(pn, p1 - 1)] - tbase);
+            int4 Tn = load_int4(tets, tet_of(min(pn, p1 - 1)));
             // phase 1c: per-row column ranges of the pieces in this batch
             uint32_t nstrips = 0;
             if ((uint32_t)lane < nb && nrows) {
@@ -798,6 +826,8 @@ __global__ void __launch_bounds__(kTileThreads)
             }
             // keeps the use of the tet record (and so its wait) after phase 1c
             asm volatile("" : "+v"(Tn.x), "+v"(Tn.y), "+v"(Tn.z), "+v"(Tn.w));
+            idx_ok = index_ok(Tn.x, nv) && index_ok(Tn.y, nv) && index_ok(Tn.z, nv) && index_ok(Tn.w, nv);
+            if (!idx_ok) Tn = make_int4(0, 0, 0, 0);
             if (pn < nend) {
                 Vn[0] = load_int4(q4, Tn.x);
                 Vn[1] = load_int4(q4, Tn.y);
@@ -823,7 +853,7 @@ __global__ void __launch_bounds__(kTileThreads)
                 }
                 double fA[4], fX[4], fY[4], fS[4], fR[4];
                 int32_t ml[4], nml[4], nkm[4];  // per face: lower mask, its complement, nk & mask
-                int32_t k0 = 0, colb = 0, di = 0, dj = 0, jend = 0;
+                int32_t k0 = 0, colb = 0, di = 0, dj = 0, jend = 0, nkr = 0;
                 uint32_t ncols = 0, pfirst = 0, pend = 0, r = 0;
                 bool first = true;
                 for (uint32_t s = sb; s < se; ++s) {
@@ -847,6 +877,7 @@ __global__ void __launch_bounds__(kTileThreads)
                             nml[fi] = ~ml[fi];
                             nkm[fi] = nk & ml[fi];
                         }
+                        nkr = nk;
                         k0 = R.k0;
                         colb = ((int32_t)R.ci0 << p.ly) + R.cj0;
                         ncols = R.ncols;
@@ -883,17 +914,16 @@ __global__ void __launch_bounds__(kTileThreads)
                             // the +1 cannot overflow, and the conversion
                             // saturates below.  A value below 0 or above nk
                             // acts as 0 or nk in the max / min that follow,
-                            // since every tet has a lower face (which gives
-                            // nk in the upper list) and an upper face (0 in
-                            // the lower list).
+                            // which include 0 and nk.
                             const double a = fma(fY[fi], ddj, fma(fX[fi], ddi, fA[fi]));
                             const double e = fmin(ceil(fma(-a, fR[fi], -0.5)), 1073741824.0);
                             const int32_t t = cvt_sat_i32(e) + (fma(fS[fi], e, a) < 0.0 ? 1 : 0);
-                            tl[fi] = t & ml[fi];
-                            tu[fi] = (t & nml[fi]) | nkm[fi];
+                            tl[fi] = fi == 0 ? t : fi == 3 ? 0 : (t & ml[fi]);
+                            tu[fi] = fi == 3 ? t : fi == 0 ? nkr : ((t & nml[fi]) | nkm[fi]);
                         }
-                        const int32_t zlo = max(max(tl[0], tl[1]), max(tl[2], tl[3]));
-                        const int32_t zhi = min(min(tu[0], tu[1]), min(tu[2], tu[3]));
+                        // slot 0 is a lower face, slot 3 an upper one
+                        const int32_t zlo = max(max(tl[0], tl[1]), max(tl[2], 0));
+                        const int32_t zhi = min(min(tu[3], tu[1]), min(tu[2], nkr));
                         if (zlo < zhi)
                             or_run_lds(s_bits + ((colb + (di << p.ly) + dj) << p.lw), k0 + zlo,
                                        k0 + zhi);
