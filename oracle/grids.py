@@ -62,3 +62,27 @@ def bricks(words, dims):
     flat = per.reshape(-1, 64)
     ids = np.nonzero(flat.any(axis=1))[0].astype(np.uint32)
     return ids, flat[ids].copy()
+
+
+def export_batch(grids, res, mode):
+    """One dense [n, res, res, res] tensor from n packed grids of any dims:
+    per axis a grid finer than res is pooled by n_a/res and a coarser one
+    repeated res/n_a times.  mode 0: float64 fraction of set voxels in each
+    cell's source block; mode 1: uint8, 1 when any voxel of the block is set.
+    ``grids``: list of (words, dims)."""
+    out = []
+    for words, dims in grids:
+        b = unpack(words, dims).astype(np.int64)
+        block = 1
+        for axis, n in enumerate(int(d) for d in dims):
+            if n > res:
+                f = n // res
+                shape = list(b.shape)
+                shape[axis:axis + 1] = [res, f]
+                b = b.reshape(shape).sum(axis=axis + 1)
+                block *= f
+        for axis, n in enumerate(int(d) for d in dims):
+            if n < res:
+                b = np.repeat(b, res // n, axis=axis)
+        out.append(b / float(block) if mode == 0 else (b > 0).astype(np.uint8))
+    return np.stack(out) if out else np.zeros((0, res, res, res))

@@ -118,3 +118,65 @@ def test_bricks_against_loops_and_reconstruction(dims):
             for v in range(8):
                 back[((8 * bx + u) * ny + 8 * by + v) * W + bz] = ws[8 * u + v]
     assert np.array_equal(back, w)
+
+
+# --- batched export: every cell checked against a per-cell loop over its
+# source block, plus closed forms (identity at res = dims, replication as a
+# Kronecker product, the set-voxel total)
+
+def export_cell_loop(words, dims, res, I, J, K):
+    """Fraction of set voxels in the source block of output cell (I, J, K),
+    read bit by bit."""
+    lo, hi = [], []
+    for X, n in zip((I, J, K), dims):
+        if n >= res:
+            f = n // res
+            lo.append(X * f)
+            hi.append(X * f + f)
+        else:
+            r = res // n
+            lo.append(X // r)
+            hi.append(X // r + 1)
+    cnt = tot = 0
+    for i in range(lo[0], hi[0]):
+        for j in range(lo[1], hi[1]):
+            for k in range(lo[2], hi[2]):
+                cnt += bit(words, dims, i, j, k)
+                tot += 1
+    return cnt / tot
+
+
+@pytest.mark.parametrize("res", [1, 2, 4, 8])
+def test_export_batch_against_cell_loops(res):
+    G = grids()
+    rng = np.random.default_rng(res)
+    items = [random_grid(rng, d)[0] for d in ((4, 8, 16), (8, 2, 4), (1, 1, 32), (8, 8, 8))]
+    dims = [(4, 8, 16), (8, 2, 4), (1, 1, 32), (8, 8, 8)]
+    frac = G.export_batch(list(zip(items, dims)), res, 0)
+    anyv = G.export_batch(list(zip(items, dims)), res, 1)
+    assert frac.shape == anyv.shape == (4, res, res, res)
+    for b, (w, d) in enumerate(zip(items, dims)):
+        for I in range(res):
+            for J in range(res):
+                for K in range(res):
+                    want = export_cell_loop(w, d, res, I, J, K)
+                    assert frac[b, I, J, K] == want
+                    assert anyv[b, I, J, K] == (1 if want > 0 else 0)
+
+
+def test_export_batch_closed_forms():
+    G = grids()
+    rng = np.random.default_rng(7)
+    w, bits = random_grid(rng, (8, 8, 8), 0.4)
+    # at the grid's own resolution the export is the unpacked grid
+    assert np.array_equal(G.export_batch([(w, (8, 8, 8))], 8, 0)[0], bits.astype(float))
+    # twice as fine: every voxel becomes a 2x2x2 block of itself
+    up = G.export_batch([(w, (8, 8, 8))], 16, 1)[0]
+    assert np.array_equal(up, np.kron(bits.astype(np.uint8), np.ones((2, 2, 2), dtype=np.uint8)))
+    # pooled: fractions times the block volume add up to the set voxels
+    down = G.export_batch([(w, (8, 8, 8))], 2, 0)[0]
+    assert down.sum() * 64 == bits.sum()
+    # a checkerboard pooled by 2 is one half everywhere
+    i, j, k = np.indices((8, 8, 8))
+    cb = ((i + j + k) % 2).astype(np.uint8)
+    assert np.all(G.export_batch([(G.pack(cb), (8, 8, 8))], 4, 0) == 0.5)
