@@ -127,7 +127,7 @@ def pregenerate(args):
         batch_meshes(args.batch_meshes)
     elif w == "serving":
         serving_pool()
-    elif w in ("grids", "quality"):
+    elif w in ("grids", "quality", "bricks"):
         make_workload("large")
         if w == "quality":
             make_workload("medium")
@@ -582,6 +582,93 @@ def bench_grids(args, torch, tv):
     print(json.dumps(res), flush=True)
 
 
+def bench_bricks(args, torch, tv):
+    """Sparse output: the large mesh voxelized straight into bricks at
+    4096^3 (a dense grid would be 8 GiB).  The timed step is one
+    tv_voxelize_bricks call; the dense path at the same resolution and the
+    sparse path at 2048^3 are timed alongside, and the bricks are decoded and
+    compared with the dense grid word for word."""
+    log("generating workload large")
+    m = make_workload("large")
+    dev = torch.device("cuda:0")
+    v = torch.from_numpy(m.verts).to(dev)
+    t = torch.from_numpy(m.tets).to(dev)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    out = {}
+    for n in (4096, 2048):
+        dims = (n, n, n)
+        nb = tv.brick_count_max(dims)
+        cap = 8 << 20
+        index = torch.empty(nb, dtype=torch.int32, device=dev)
+        pool = torch.empty((cap, 64), dtype=torch.int32, device=dev)
+        ids = torch.empty(cap, dtype=torch.int32, device=dev)
+        count = torch.empty(1, dtype=torch.int32, device=dev)
+        ws = tv.alloc_workspace(max(tv.bricks_workspace_bytes(m.nv, m.nt, dims),
+                                    tv.workspace_bytes(m.nv, m.nt, dims)), dev)
+
+        def step():
+            tv.voxelize_bricks(v, t, dims, m.bbox, cap, index=index, pool=pool, ids=ids, count=count,
+                               workspace=ws, stream=stream)
+        steps = args.steps if n == 4096 else 5
+        ms = timed(step, steps, args.warmup)
+        assert tv.fetch_status(ws) == tv.TV_OK
+        idx = index.long() & 0xFFFFFFFF
+        full = int((idx == 0xFFFFFFFF).sum())
+        mixed = int(((idx != 0) & (idx != 0xFFFFFFFF)).sum())
+        taken = int(count.item())
+        # the dense path at the same resolution, and a word-for-word check
+        grid = tv.alloc_grid(dims, dev)
+        ms_dense = timed(lambda: tv.voxelize(v, t, dims, m.bbox, grid=grid, workspace=ws, stream=stream),
+                         3 if n == 4096 else 5, 1)
+        nx = ny = nz = n
+        W = nz // 32
+        lanes = torch.arange(64, device=dev)
+        u_, v_ = lanes // 8, lanes % 8
+        nby, nbz = ny // 8, nz // 32
+
+        def positions(b):
+            bx, by, bz = b // (nby * nbz), (b // nbz) % nby, b % nbz
+            return (((8 * bx[:, None] + u_) * ny + (8 * by[:, None] + v_)) * W + bz[:, None]).reshape(-1)
+
+        sid = ids[:min(taken, cap)].long() & 0xFFFFFFFF
+        live = sid != 0xFFFFFFFF
+        dec = torch.zeros_like(grid)
+        dec[positions(torch.nonzero(idx == 0xFFFFFFFF).reshape(-1))] = -1
+        dec[positions(sid[live])] = pool[:min(taken, cap)][live].reshape(-1)
+        same = bool(torch.equal(dec, grid))
+        del dec, grid, index, pool, ids, ws
+        torch.cuda.empty_cache()
+        sparse_bytes = 4 * nb + 256 * mixed
+        rec = {"ms": ms, "tets_per_s": m.nt / (ms * 1e-3), "dense_path_ms": ms_dense, "bricks": nb,
+               "full_bricks": full, "pooled_bricks": mixed, "slots_taken": taken,
+               "sparse_bytes": sparse_bytes, "dense_bytes": nx * ny * W * 4,
+               "compression": nx * ny * W * 4 / sparse_bytes, "bit_identical_to_dense": same}
+        log(f"bricks {n}^3: {rec}")
+        out[str(n)] = rec
+    r = out["4096"]
+    res = {"metric": "tets voxelized/s (sparse bricks, no dense grid)", "value": r["tets_per_s"],
+           "unit": "tets/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic (seeded jittered Kuhn mesh)",
+           "config": {"workload": "large mesh into 8x8x32 bricks at 4096^3", "grid": [4096] * 3,
+                      "tets": m.nt},
+           "bricks": out}
+    print(json.dumps(res), flush=True)
+
+
 QUALITY_OPS_PER_TET = 6 * 60 + 20  # six dihedral angles (cross products, norms, sqrt, acos) + exact 6V
 
 
@@ -846,7 +933,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="large",
-                    choices=["large", "medium", "small", "batch", "serving", "grids", "quality", "sweep",
+                    choices=["large", "medium", "small", "batch", "serving", "grids", "quality", "sweep", "bricks",
                              "tune"])
     ap.add_argument("--requests", type=int, default=10000)
     ap.add_argument("--batch-meshes", type=int, default=1024)
@@ -891,6 +978,8 @@ def main():
         return bench_serving(args, torch, tv)
     if args.workload == "grids":
         return bench_grids(args, torch, tv)
+    if args.workload == "bricks":
+        return bench_bricks(args, torch, tv)
     if args.workload == "quality":
         return bench_quality(args, torch, tv)
     if args.workload == "sweep":

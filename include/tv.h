@@ -270,6 +270,8 @@ tv_status tv_snap(const float *verts, int64_t nv, tv_bbox bbox, int32_t *q_out, 
  * position for a batch).  Synchronizes `stream`, then returns TV_OK,
  * TV_ERR_INDEX or TV_ERR_RANGE (TV_ERR_INDEX wins when both occurred), or
  * TV_ERR_INVALID_ARG (index outside the last call's meshes) / TV_ERR_HIP.
+ * After tv_voxelize_bricks it also reports TV_ERR_TOO_LARGE (brick pool
+ * too small), after the other two.
  */
 tv_status tv_fetch_status(const void *ws, int32_t mesh_index, void *stream);
 
@@ -419,6 +421,72 @@ tv_status tv_unpack(const uint32_t *grid, tv_dims dims, void *out, uint32_t form
 #define TV_POOL_ANY 1u
 tv_status tv_pool(const uint32_t *grid, tv_dims dims, int32_t factor, uint32_t mode, void *out,
                   void *stream);
+
+/*
+ * tv_export_batch: many grids of any dims (for instance the grids of one
+ * tv_voxelize_batch call) into ONE dense tensor out[n][res][res][res] (C
+ * order, z fastest) for a 3D CNN, in one kernel launch.  Per axis, a grid
+ * finer than res is pooled by n_a / res and a coarser one repeats each voxel
+ * res / n_a times, so every grid lands at the common resolution res.  The
+ * value of a cell, from its source block (the voxels it pools, or the one
+ * voxel it repeats):
+ *   TV_EXPORT_FRACTION: float32, set voxels of the block / voxels of the
+ *     block (exact: a multiple of a power of two);
+ *   TV_EXPORT_ANY: uint8, 1 when any voxel of the block is set.
+ * `grids` is a HOST array of n (device grid pointer, dims) pairs; it is
+ * copied into `ws` (device, 256-byte aligned, tv_export_workspace_bytes(n)
+ * bytes) during the call, so the call must not be captured in a graph.
+ * res: a power of two in [1, 1024]; a pooled block may hold at most 2^24
+ * voxels.  Errors: TV_ERR_INVALID_ARG (null, n, res, mode, block size),
+ * TV_ERR_UNSUPPORTED_DIMS (a grid's dims), TV_ERR_WORKSPACE.
+ */
+typedef struct {
+    const uint32_t *grid; /* device, packed layout above */
+    tv_dims dims;
+} tv_grid_ref;
+#define TV_EXPORT_FRACTION 0u
+#define TV_EXPORT_ANY 1u
+size_t tv_export_workspace_bytes(int32_t n);
+tv_status tv_export_batch(const tv_grid_ref *grids, int32_t n, int32_t res, uint32_t mode, void *out,
+                          void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * tv_voxelize_bricks: voxelize one mesh (fp32 world coordinates, as
+ * tv_voxelize) straight into sparse bricks, with no dense grid -- for grids
+ * whose dense form is not worth keeping (a 4096^3 grid is 8 GiB; the paper's
+ * Octrees paragraph, Section 5, discusses sparse storage of such data).  A
+ * brick is 8 x 8 columns by 32 z voxels, laid out as in tv_bricks below:
+ * brick (bx, by, bz) has id (bx*(ny/8) + by)*(nz/32) + bz and word u*8 + v
+ * of a brick is word bz of column (8bx+u, 8by+v).  Outputs (device, owned by
+ * the caller):
+ *   index     [tv_brick_count_max(dims)] uint32, written entirely: 0 for an
+ *             empty brick, TV_BRICK_FULL when every voxel of the brick is
+ *             set, otherwise 1 + the brick's slot in pool;
+ *   pool      [capacity][64] uint32: the words of the slotted bricks;
+ *   pool_ids  [capacity] uint32: the brick id of each slot, or
+ *             TV_BRICK_UNUSED for a slot given up (several writers can race
+ *             for a brick; the losers merge into the winner's slot);
+ *   pool_count one uint32: the slots taken, including given-up ones.
+ * A brick is in the pool iff it is neither empty nor full, so the bricks are
+ * unique; their slot order is not.  Each tile of the grid is voxelized by
+ * one workgroup, so the slots taken are the pooled bricks plus the few given
+ * up where two tets too large for the tile pipeline race for a new brick.
+ * If pool_count exceeds capacity the output is incomplete and the data-error
+ * status (tv_fetch_status(ws, 0, stream)) reads TV_ERR_TOO_LARGE: call again
+ * with capacity >= pool_count.
+ * dims: powers of two with nx, ny >= 8 and nz >= 32, at most 2^32 - 2
+ * bricks.  ws: tv_voxelize_bricks_workspace_bytes(nv, nt, dims) bytes (the
+ * dense call's workspace with room for up to 27 tiles per tet, about 16
+ * bytes per vertex plus 120 per tet).  flags: 0 or TV_TIE_STRICT.  Enqueues
+ * kernels only (graph-capturable).
+ */
+#define TV_BRICK_FULL 0xffffffffu
+#define TV_BRICK_UNUSED 0xffffffffu
+size_t tv_voxelize_bricks_workspace_bytes(int64_t nv, int64_t nt, tv_dims dims);
+tv_status tv_voxelize_bricks(const float *verts, int64_t nv, const int32_t *tets, int64_t nt,
+                             tv_dims dims, tv_bbox bbox, uint32_t *index, uint32_t *pool,
+                             uint32_t *pool_ids, int64_t capacity, uint32_t *pool_count, void *ws,
+                             size_t ws_bytes, void *stream, uint32_t flags);
 
 /*
  * tv_bricks: the non-empty bricks of a grid, in increasing brick id.  A

@@ -48,8 +48,13 @@ EXPORTED = ("tv_grid_words", "tv_workspace_bytes", "tv_voxelize", "tv_voxelize_q
             "tv_server_release", "tv_server_get_stats", "tv_server_destroy", "tv_unpack", "tv_pool",
             "tv_brick_count_max", "tv_bricks_workspace_bytes", "tv_bricks", "tv_read_mesh",
             "tv_free_host_mesh", "tv_quality_workspace_bytes", "tv_mesh_quality",
-            "tv_voxelize_pipelined", "tv_voxelize_noalloc")
+            "tv_voxelize_pipelined", "tv_voxelize_noalloc", "tv_export_workspace_bytes", "tv_export_batch",
+            "tv_voxelize_bricks", "tv_voxelize_bricks_workspace_bytes")
 
+BRICK_FULL = 0xFFFFFFFF
+BRICK_UNUSED = 0xFFFFFFFF
+EXPORT_FRACTION = 0
+EXPORT_ANY = 1
 UNPACK_U8 = 0
 UNPACK_F32 = 1
 POOL_FRACTION = 0
@@ -94,6 +99,10 @@ class ParamsC(ctypes.Structure):
 class HostMeshC(ctypes.Structure):
     _fields_ = [("verts", ctypes.c_void_p), ("nv", ctypes.c_int64), ("tets", ctypes.c_void_p),
                 ("nt", ctypes.c_int64), ("bbox", BBox), ("skipped_elements", ctypes.c_int64)]
+
+
+class GridRefC(ctypes.Structure):
+    _fields_ = [("grid", ctypes.c_void_p), ("dims", Dims)]
 
 
 class QualityC(ctypes.Structure):
@@ -165,6 +174,10 @@ def load_library():
     lib.tv_voxelize_q.restype = st
     lib.tv_voxelize_noalloc.argtypes = [P, i64, P, i64, Dims, BBox, P, P, P, u32]
     lib.tv_voxelize_noalloc.restype = st
+    lib.tv_voxelize_bricks.argtypes = [P, i64, P, i64, Dims, BBox, P, P, P, i64, P, P, ctypes.c_size_t, P, u32]
+    lib.tv_voxelize_bricks.restype = st
+    lib.tv_voxelize_bricks_workspace_bytes.argtypes = [i64, i64, Dims]
+    lib.tv_voxelize_bricks_workspace_bytes.restype = ctypes.c_size_t
     lib.tv_batch_workspace_bytes.argtypes = [P, ctypes.c_int32, u32]
     lib.tv_batch_workspace_bytes.restype = ctypes.c_size_t
     lib.tv_voxelize_batch.argtypes = [P, ctypes.c_int32, P, ctypes.c_size_t, P, u32]
@@ -230,6 +243,10 @@ def load_library():
     lib.tv_bricks_workspace_bytes.restype = ctypes.c_size_t
     lib.tv_bricks.argtypes = [P, Dims, P, P, i64, P, P, ctypes.c_size_t, P]
     lib.tv_bricks.restype = st
+    lib.tv_export_workspace_bytes.argtypes = [ctypes.c_int32]
+    lib.tv_export_workspace_bytes.restype = ctypes.c_size_t
+    lib.tv_export_batch.argtypes = [P, ctypes.c_int32, ctypes.c_int32, u32, P, P, ctypes.c_size_t, P]
+    lib.tv_export_batch.restype = st
     _lib = lib
     return lib
 
@@ -370,6 +387,84 @@ def voxelize_noalloc(verts, tets, dims, bbox, *, strict=False, grid=None, status
                                  TIE_STRICT if strict else TIE_HALF_OPEN)
     _check(rc)
     return grid, status
+
+
+def export_batch(grids, res, mode="fraction", *, out=None, workspace=None, stream=None):
+    """Many grids of any dims -> one dense [n, res, res, res] tensor in one
+    launch (tv_export_batch): float32 fractions (``mode="fraction"``) or
+    uint8 occupancy (``mode="any"``).  ``grids``: list of (grid tensor, dims)."""
+    lib = load_library()
+    torch = _torch()
+    n = len(grids)
+    if n == 0:
+        raise ValueError("no grids")
+    code = {"fraction": EXPORT_FRACTION, "any": EXPORT_ANY}[mode]
+    arr = (GridRefC * n)()
+    for i, (g, dims) in enumerate(grids):
+        gptr, _ = _dev_ptr(g, torch.int32, None, f"grids[{i}]")
+        if g.numel() < grid_words(dims):
+            raise ValueError(f"grids[{i}] tensor too small for dims {dims}")
+        arr[i] = GridRefC(gptr, _dims(dims))
+    dev = grids[0][0].device
+    dt = torch.float32 if code == EXPORT_FRACTION else torch.uint8
+    if out is None:
+        out = torch.empty((n, res, res, res), dtype=dt, device=dev)
+    optr, _ = _dev_ptr(out, dt, None, "out")
+    if out.numel() < n * res ** 3:
+        raise ValueError("out too small")
+    need = int(lib.tv_export_workspace_bytes(n))
+    if workspace is None:
+        workspace = alloc_workspace(need, dev)
+    wptr, _ = _dev_ptr(workspace, torch.uint8, None, "workspace")
+    _check(lib.tv_export_batch(ctypes.cast(arr, ctypes.c_void_p), n, int(res), code, optr, wptr,
+                               workspace.numel(), _stream_handle(stream)))
+    return out
+
+
+def bricks_workspace_bytes(nv: int, nt: int, dims) -> int:
+    return int(load_library().tv_voxelize_bricks_workspace_bytes(int(nv), int(nt), _dims(dims)))
+
+
+def brick_count_max(dims) -> int:
+    return int(load_library().tv_brick_count_max(_dims(dims)))
+
+
+def voxelize_bricks(verts, tets, dims, bbox, capacity, *, strict=False, index=None, pool=None, ids=None,
+                    count=None, workspace=None, stream=None):
+    """Voxelize one mesh (fp32 world coordinates) straight into sparse bricks
+    (tv_voxelize_bricks).  Returns (index, pool, ids, count, workspace): int32
+    tensors holding the uint32 outputs (index [bricks], pool [capacity, 64],
+    ids [capacity], count [1]); read data errors and pool overflow with
+    ``fetch_status(workspace)``."""
+    lib = load_library()
+    torch = _torch()
+    vptr, nv = _dev_ptr(verts, torch.float32, 3, "verts")
+    tptr, nt = _dev_ptr(tets, torch.int32, 4, "tets")
+    dev = verts.device
+    nb = brick_count_max(dims)
+    capacity = int(capacity)
+    if index is None:
+        index = torch.empty(max(nb, 1), dtype=torch.int32, device=dev)
+    if pool is None:
+        pool = torch.empty((max(capacity, 1), 64), dtype=torch.int32, device=dev)
+    if ids is None:
+        ids = torch.empty(max(capacity, 1), dtype=torch.int32, device=dev)
+    if count is None:
+        count = torch.empty(1, dtype=torch.int32, device=dev)
+    if index.numel() < nb or pool.numel() < 64 * capacity or ids.numel() < capacity:
+        raise ValueError("index, pool or ids too small")
+    iptr, _ = _dev_ptr(index, torch.int32, None, "index")
+    pptr, _ = _dev_ptr(pool, torch.int32, None, "pool")
+    dptr, _ = _dev_ptr(ids, torch.int32, None, "ids")
+    cptr, _ = _dev_ptr(count, torch.int32, None, "count")
+    flags = TIE_STRICT if strict else TIE_HALF_OPEN
+    need = bricks_workspace_bytes(nv, nt, dims)
+    if workspace is None:
+        workspace = alloc_workspace(need, dev)
+    wptr, _ = _dev_ptr(workspace, torch.uint8, None, "workspace")
+    _check(lib.tv_voxelize_bricks(vptr, nv, tptr, nt, _dims(dims), _bbox(bbox), iptr, pptr, dptr, capacity, cptr,
+                                  wptr, workspace.numel(), _stream_handle(stream), flags))
+    return index, pool, ids, count, workspace
 
 
 def voxelize_pipelined(verts_host, tets_host, dims, bbox, chunks=8, *, strict=False, per_tet=False,

@@ -235,7 +235,7 @@ tv_status enqueue(const tv::MeshTable &T, const tv::CallSizes &c, uint8_t *ws, h
         tv::launch_bin_count(T, b, s);
         tv::launch_scan_tiles(T, b, s);
         tv::launch_bin_scatter(T, b, s);
-        if (!accumulate) tv::launch_zero_shared_tiles(T, b, s);
+        if (!accumulate && !T.bricks.index) tv::launch_zero_shared_tiles(T, b, s);
     }
     if ((st = check_hip("binning launch"))) return st;
     const int cus = device_cus();
@@ -246,6 +246,7 @@ tv_status enqueue(const tv::MeshTable &T, const tv::CallSizes &c, uint8_t *ws, h
     {
         tv::StageScope sc(tv::kStageLarge, s);
         tv::launch_large_tets(T, b, strict, cus, s);
+        if (T.bricks.index) tv::launch_bricks_canonical(T, b, 4 * cus, s);
     }
     return check_hip("voxelize launch");
 }
@@ -428,6 +429,62 @@ tv_status tv_voxelize_q(const int32_t *qverts, int64_t nv, const int32_t *tets, 
                         uint32_t flags) {
     return voxelize_one(qverts, TV_VERTS_Q32, nv, tets, nt, dims, nullptr, grid, ws, ws_bytes,
                         stream, flags);
+}
+
+size_t tv_voxelize_bricks_workspace_bytes(int64_t nv, int64_t nt, tv_dims dims) {
+    if (nv < 0 || nt < 0 || !tv_grid_words(dims)) return 0;
+    const tv::Params P = current_params(0);
+    tv::CallSizes c = {1, nv, nt, tv::plan_tiles(dims, P.min_tiles, P.tile_cols_log2).ntiles};
+    c.piece_slots = tv::kPieceCapSparse;
+    return tv::layout(c).total;
+}
+
+tv_status tv_voxelize_bricks(const float *verts, int64_t nv, const int32_t *tets, int64_t nt,
+                             tv_dims dims, tv_bbox bbox, uint32_t *index, uint32_t *pool,
+                             uint32_t *pool_ids, int64_t capacity, uint32_t *pool_count, void *ws,
+                             size_t ws_bytes, void *stream, uint32_t flags) {
+    if (!pow2_dim(dims.nx) || !pow2_dim(dims.ny) || !pow2_dim(dims.nz) || dims.nx < 8 || dims.ny < 8 ||
+        dims.nz < 32)
+        return fail(TV_ERR_UNSUPPORTED_DIMS,
+                    "bricks: dims (%d,%d,%d) must be powers of two with nx, ny >= 8 and nz >= 32",
+                    dims.nx, dims.ny, dims.nz);
+    const int64_t nbx = dims.nx / 8, nby = dims.ny / 8, nbz = dims.nz / 32;
+    const int64_t nbricks = nbx * nby * nbz;
+    if (nbricks > (int64_t)0xfffffffe)
+        return fail(TV_ERR_UNSUPPORTED_DIMS, "bricks: %lld bricks do not fit 32-bit ids", (long long)nbricks);
+    if (!index || !pool_count || capacity < 0 || (capacity > 0 && (!pool || !pool_ids)) ||
+        capacity > ((int64_t)1 << 32) - 2)
+        return fail(TV_ERR_INVALID_ARG, "bricks: null output or bad capacity %lld", (long long)capacity);
+    if (flags & ~(uint32_t)TV_TIE_STRICT)
+        return fail(TV_ERR_INVALID_ARG, "bricks: takes TV_TIE_STRICT only (flags 0x%x)", flags);
+    if (nt > ((int64_t)1 << 32) / tv::kPieceCapSparse)
+        return fail(TV_ERR_INVALID_ARG, "bricks: %lld tets exceed the piece slots", (long long)nt);
+    // the index stands in for the grid in the shared checks (only its
+    // presence and alignment are looked at)
+    tv_status st = check_mesh_impl(verts, TV_VERTS_F32, nv, tets, nt, dims, &bbox, index, "");
+    if (st) return st;
+    const tv::Params P = current_params(0);
+    if ((st = check_ws(ws, ws_bytes, tv_voxelize_bricks_workspace_bytes(nv, nt, dims), flags))) return st;
+    tv::MeshDesc d = make_desc_impl(verts, TV_VERTS_F32, nv, tets, nt, dims, &bbox, nullptr, P);
+    tv::CallSizes c = {1, nv, nt, d.p.ntiles, false};
+    c.piece_slots = tv::kPieceCapSparse;
+    tv::MeshTable T = make_table(c, static_cast<uint8_t *>(ws), &d, flags, P);
+    // one task per tile, so that a brick has one writer (large tets aside)
+    // and the pool holds no slots given up in races between tasks; tets
+    // meeting up to 27 tiles go through the tile pipeline
+    T.chunk = 1 << 30;
+    T.piece_cap = tv::kPieceCapSparse;
+    T.bricks.index = index;
+    T.bricks.pool = pool;
+    T.bricks.ids = pool_ids;
+    T.bricks.count = pool_count;
+    T.bricks.capacity = capacity;
+    T.bricks.nby = (int32_t)nby;
+    T.bricks.nbz = (int32_t)nbz;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    tv::launch_clear(index, nbricks, s);
+    tv::launch_set_word(pool_count, 0u, s);
+    return enqueue(T, c, static_cast<uint8_t *>(ws), s, flags, &d, 1, P.wgs_per_cu);
 }
 
 size_t tv_batch_workspace_bytes(const tv_mesh *meshes, int32_t n, uint32_t flags) {
@@ -650,6 +707,7 @@ tv_status tv_fetch_status(const void *ws, int32_t mesh_index, void *stream) {
         return fail(TV_ERR_HIP, "reading the status word failed");
     if (word & tv::kStatusIndex) return TV_ERR_INDEX;
     if (word & tv::kStatusRange) return TV_ERR_RANGE;
+    if (word & tv::kStatusFull) return TV_ERR_TOO_LARGE;
     return TV_OK;
 }
 

@@ -26,6 +26,7 @@ constexpr int32_t kQMax = 65536 + 16384;
 // device status bits (per mesh)
 constexpr uint32_t kStatusIndex = 1u;  // tet index outside [0, nv)
 constexpr uint32_t kStatusRange = 2u;  // NaN / off-lattice coordinate
+constexpr uint32_t kStatusFull = 4u;   // sparse output: more bricks than the pool holds
 
 struct GridGeom {
     int32_t n[3];      // voxels per axis (powers of two)

@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "tv.h"
 #include "tv_internal.h"
 
@@ -264,6 +266,61 @@ __global__ void __launch_bounds__(kThreads)
     }
 }
 
+// ----------------------------------------------------------- batch export
+
+// One grid of a batch export: device pointer, log2 of its dims, words per
+// column.
+struct ExportRef {
+    const uint32_t *grid;
+    int32_t ln[3];
+    int32_t words;
+};
+
+// One thread per output cell (grid-stride): per axis the cell's source range
+// is a block of 2^(ln - lres) voxels (pooled axis) or the single voxel it
+// repeats; the set voxels of the block are counted word by word along z.
+template <bool kFraction>
+__global__ void __launch_bounds__(kThreads)
+    k_export(const ExportRef *__restrict__ tab, int64_t total, int32_t lres, void *__restrict__ out) {
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    const int32_t cmask = (1 << lres) - 1;
+    for (int64_t o = (int64_t)blockIdx.x * kThreads + threadIdx.x; o < total; o += stride) {
+        const ExportRef g = tab[o >> (3 * lres)];
+        const int32_t c[3] = {(int32_t)(o >> (2 * lres)) & cmask, (int32_t)(o >> lres) & cmask,
+                              (int32_t)o & cmask};
+        int32_t lo[3], len[3], lblock = 0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int32_t d = g.ln[a] - lres;
+            lo[a] = d >= 0 ? c[a] << d : c[a] >> -d;
+            len[a] = d >= 0 ? 1 << d : 1;
+            lblock += d >= 0 ? d : 0;
+        }
+        const int32_t k0 = lo[2], k1 = lo[2] + len[2] - 1, w0 = k0 >> 5, w1 = k1 >> 5;
+        uint32_t cnt = 0;
+        for (int32_t i = lo[0]; i < lo[0] + len[0]; ++i)
+            for (int32_t j = lo[1]; j < lo[1] + len[1]; ++j) {
+                const uint32_t *col = g.grid + (((int64_t)i << g.ln[1]) + j) * g.words;
+                for (int32_t w = w0; w <= w1; ++w) {
+                    uint32_t m = 0xffffffffu;
+                    if (w == w0) m &= 0xffffffffu << (k0 & 31);
+                    if (w == w1) m &= 0xffffffffu >> (31 - (k1 & 31));
+                    cnt += (uint32_t)__popc(col[w] & m);
+                }
+            }
+        // a block holds at most 2^24 voxels, so the count and the fraction
+        // (count * 2^-lblock) are exact in float
+        if (kFraction) static_cast<float *>(out)[o] = ldexpf((float)cnt, -lblock);
+        else static_cast<uint8_t *>(out)[o] = cnt ? 1 : 0;
+    }
+}
+
+int32_t log2_exact(int32_t n) {
+    int32_t l = 0;
+    while ((1 << l) < n) ++l;
+    return l;
+}
+
 }  // namespace
 
 extern "C" {
@@ -368,6 +425,50 @@ tv_status tv_bricks(const uint32_t *grid, tv_dims dims, uint32_t *ids, uint32_t 
     k_brick_write<<<(unsigned)nblocks, kThreads, 0, s>>>(grid, dims.ny, words, nby, nbz, nb, block,
                                                          capacity, ids, brick_words);
     return launched("bricks launch");
+}
+
+size_t tv_export_workspace_bytes(int32_t n) {
+    if (n <= 0) return 0;
+    return ((size_t)n * sizeof(ExportRef) + 255) & ~(size_t)255;
+}
+
+tv_status tv_export_batch(const tv_grid_ref *grids, int32_t n, int32_t res, uint32_t mode, void *out,
+                          void *ws, size_t ws_bytes, void *stream) {
+    if (!grids || n <= 0 || !out)
+        return tv::set_error(TV_ERR_INVALID_ARG, "export: need grids, n > 0 and an output");
+    if (res < 1 || res > 1024 || (res & (res - 1)))
+        return tv::set_error(TV_ERR_INVALID_ARG, "export: res %d is not a power of two in [1, 1024]", res);
+    if (mode != TV_EXPORT_FRACTION && mode != TV_EXPORT_ANY)
+        return tv::set_error(TV_ERR_INVALID_ARG, "export: unknown mode %u", mode);
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255u) || ws_bytes < tv_export_workspace_bytes(n))
+        return tv::set_error(TV_ERR_WORKSPACE, "export: workspace null, misaligned or below %zu bytes",
+                             tv_export_workspace_bytes(n));
+    const int32_t lres = log2_exact(res);
+    std::vector<ExportRef> tab((size_t)n);
+    for (int32_t i = 0; i < n; ++i) {
+        const tv_grid_ref &r = grids[i];
+        if (!r.grid) return tv::set_error(TV_ERR_INVALID_ARG, "export: grid %d is null", i);
+        if (!dims_ok(r.dims))
+            return tv::set_error(TV_ERR_UNSUPPORTED_DIMS, "export: grid %d dims (%d,%d,%d)", i, r.dims.nx,
+                                 r.dims.ny, r.dims.nz);
+        const int32_t ln[3] = {log2_exact(r.dims.nx), log2_exact(r.dims.ny), log2_exact(r.dims.nz)};
+        int32_t lblock = 0;
+        for (int a = 0; a < 3; ++a) lblock += ln[a] > lres ? ln[a] - lres : 0;
+        if (lblock > 24)
+            return tv::set_error(TV_ERR_INVALID_ARG, "export: grid %d pools blocks of 2^%d voxels (at most 2^24)",
+                                 i, lblock);
+        tab[(size_t)i] = {r.grid, {ln[0], ln[1], ln[2]}, (r.dims.nz + 31) / 32};
+    }
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    if (hipMemcpyAsync(ws, tab.data(), sizeof(ExportRef) * tab.size(), hipMemcpyHostToDevice, s) != hipSuccess)
+        return tv::set_error(TV_ERR_HIP, "export: table upload failed");
+    const int64_t total = (int64_t)n << (3 * lres);
+    const int64_t want = (total + kThreads - 1) / kThreads;
+    const unsigned blocks = (unsigned)(want < 65536 ? want : 65536);
+    const ExportRef *dtab = static_cast<const ExportRef *>(ws);
+    if (mode == TV_EXPORT_FRACTION) k_export<true><<<blocks, kThreads, 0, s>>>(dtab, total, lres, out);
+    else k_export<false><<<blocks, kThreads, 0, s>>>(dtab, total, lres, out);
+    return launched("export launch");
 }
 
 }  // extern "C"

@@ -43,6 +43,22 @@ struct MeshDesc {
                          // order, never binned (the tile kernel checks their indices)
 };
 
+// Sparse output of a single-mesh call: bricks of 8 x 8 columns x 32 z
+// voxels (one grid word per column).  index[brick id]: 0 empty, kBrickFull
+// every voxel set, else 1 + the brick's slot; pool[slot][64] the brick's
+// words (column (8bx+u, 8by+v) at word u*8 + v); ids[slot] the brick of a
+// slot (kBrickUnused for a slot given up in a race); *count the slots taken.
+constexpr uint32_t kBrickFull = 0xffffffffu;
+constexpr uint32_t kBrickUnused = 0xffffffffu;
+struct BrickOut {
+    uint32_t *index;
+    uint32_t *pool;
+    uint32_t *ids;
+    uint32_t *count;
+    int64_t capacity;
+    int32_t nby, nbz;  // bricks per y row (ny / 8) and per column (nz / 32)
+};
+
 // The meshes of one call.  A single mesh travels by value in `one`; a batch
 // lives in device memory with prefix sums over vertices, tets and tiles
 // (each [n + 1]) that map a global index to its mesh.
@@ -59,6 +75,7 @@ struct MeshTable {
     int32_t nocull;     // boxes of at most this many columns skip row culling
     int64_t nv_total, nt_total, ntiles_total;
     MeshDesc one;
+    BrickOut bricks;    // sparse output (single-mesh calls), used when bricks.index != nullptr
 };
 
 // meta[] slots
@@ -95,6 +112,7 @@ void launch_tile_voxelize(const MeshTable &T, const BinBuffers &b, bool strict, 
 void launch_large_tets(const MeshTable &T, const BinBuffers &b, bool strict, int workgroups,
                        hipStream_t s);
 void launch_voxelize_per_tet(const MeshDesc &d, const BinBuffers &b, bool strict, hipStream_t s);
+void launch_bricks_canonical(const MeshTable &T, const BinBuffers &b, int workgroups, hipStream_t s);
 int tile_max_words();
 
 }  // namespace tv

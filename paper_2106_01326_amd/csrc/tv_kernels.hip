@@ -224,6 +224,9 @@ constexpr int64_t kBinTetsMany = (int64_t)1 << 21;
 constexpr int kHashSlots = 512;
 constexpr int kHashProbes = 32;
 constexpr int kPieceCapMax = 8;
+// sparse-output calls: up to 3 x 3 x 3 tiles per tet go through the tile
+// pipeline (at 4096^3 a tet of the 128^3-cube mesh meets up to 18 tiles)
+constexpr int kPieceCapBricks = 27;
 constexpr uint32_t kEmptyKey = 0xffffffffu;
 constexpr uint32_t kNoSlot = 0xffffffffu;
 
@@ -254,11 +257,11 @@ __device__ __forceinline__ uint2 encode_trec(uint32_t key0, const TileRange &r, 
                                 (uint32_t)(r.z1 - r.z0) << 7);
 }
 
-template <bool kScatter, int kBinTets, bool kTable>
+template <bool kScatter, int kBinTets, bool kTable, int kCap = kPieceCapMax>
 __global__ void __launch_bounds__(kBinThreads) k_bin(MeshTable T, BinBuffers b) {
     __shared__ uint32_t s_key[kHashSlots];
     __shared__ uint32_t s_cnt[kHashSlots];  // count, then (pass 2) global slot base
-    __shared__ uint32_t s_ref[kBinTets * kBinThreads * kPieceCapMax];  // slot << 16 | rank, or kNoSlot
+    __shared__ uint32_t s_ref[kBinTets * kBinThreads * kCap];  // slot << 16 | rank, or kNoSlot
     __shared__ int32_t s_bracket[2];
     const int tid = threadIdx.x;
     for (int i = tid; i < kHashSlots; i += kBinThreads) {
@@ -284,7 +287,8 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(MeshTable T, BinBuffers b) 
         } else if (!kScatter) {
             TileRange r = {0, -1, 0, -1, 0, -1};
             int32_t n = tet_pieces(d, b.q4, t - d.tet_base, b.status, r);
-            if (n > T.piece_cap) {
+            // (the summary holds at most 8 tiles per axis)
+            if (n > T.piece_cap || r.x1 - r.x0 > 7 || r.y1 - r.y0 > 7 || r.z1 - r.z0 > 7) {
                 b.big[atomicAdd(&b.meta[kMetaBig], 1u)] = (uint32_t)t;
                 n = 0;
             }
@@ -347,7 +351,7 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(MeshTable T, BinBuffers b) 
                 ref = (h << 16) | atomicAdd(s_cnt + h, 1u);
             else
                 b.pieces[b.tile_off[key] + atomicAdd(b.tile_cursor + key, 1u)] = (uint32_t)t;
-            s_ref[(u * kBinThreads + tid) * kPieceCapMax + k] = ref;
+            s_ref[(u * kBinThreads + tid) * kCap + k] = ref;
         }
     }
     __syncthreads();
@@ -363,7 +367,7 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(MeshTable T, BinBuffers b) 
     for (int u = 0; u < kBinTets; ++u) {
         const int64_t t = first + u * kBinThreads + tid;
         for (int32_t k = 0; k < np[u]; ++k) {
-            const uint32_t ref = s_ref[(u * kBinThreads + tid) * kPieceCapMax + k];
+            const uint32_t ref = s_ref[(u * kBinThreads + tid) * kCap + k];
             if (ref != kNoSlot) b.pieces[s_cnt[ref >> 16] + (ref & 0xffffu)] = (uint32_t)t;
         }
     }
@@ -595,6 +599,77 @@ __device__ __forceinline__ void row_columns(const RowHull &h, double cx, const G
     const double S = (double)g.half[1], inv = ldexp(1.0, -g.shift[1]);  // 1 / 2S
     j0 = (int32_t)ceil((ylo - 1.0 - S) * inv);
     j1 = (int32_t)floor((yhi + 1.0 - S) * inv);
+}
+
+
+// ------------------------------------------------------- sparse (bricks)
+
+__device__ __forceinline__ uint32_t load_agent(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Merges one brick's contribution into the sparse output; called by a whole
+// wave, lane l holding word l (column (8bx+u, 8by+v) at l = u*8 + v).  A
+// brick already in the pool is ORed into; a new one either becomes
+// kBrickFull (every word all ones) or takes a fresh slot: the words are
+// written, then the slot is published with a compare-and-swap on the index.
+// A writer that loses that race gives its slot up (ids = kBrickUnused) and
+// merges into the winner's.  Several writers meet a brick only when its
+// tile is shared by several tasks or a large tet covers it.
+__device__ void brick_merge_wave(const BrickOut &o, uint32_t id, uint32_t word, int lane,
+                                 uint32_t *status) {
+    if (__ballot(word != 0u) == 0ull) return;
+    const bool full = __ballot(word == 0xffffffffu) == ~0ull;
+    uint32_t cur = __shfl(lane == 0 ? load_agent(o.index + id) : 0u, 0);
+    for (;;) {
+        if (cur == kBrickFull) return;
+        if (cur != 0u) {
+            if (word)
+                __hip_atomic_fetch_or(o.pool + (size_t)(cur - 1u) * 64u + lane, word, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
+            return;
+        }
+        uint32_t prev = 0;
+        if (full) {
+            if (lane == 0) prev = atomicCAS(o.index + id, 0u, kBrickFull);
+            prev = __shfl(prev, 0);
+        } else {
+            uint32_t slot = 0;
+            if (lane == 0) slot = atomicAdd(o.count, 1u);
+            slot = __shfl(slot, 0);
+            if ((int64_t)slot >= o.capacity) {
+                if (lane == 0) atomicOr(status, kStatusFull);
+                return;
+            }
+            o.pool[(size_t)slot * 64u + lane] = word;
+            if (lane == 0) o.ids[slot] = id;
+            __threadfence();
+            if (lane == 0) prev = atomicCAS(o.index + id, 0u, slot + 1u);
+            prev = __shfl(prev, 0);
+            if (prev != 0u && lane == 0) o.ids[slot] = kBrickUnused;
+        }
+        if (prev == 0u) return;
+        cur = prev;
+    }
+}
+
+// The bricks of a tile bitmap in LDS (tile of 2^lx x 2^ly columns, lx and
+// ly >= 3, by 2^lw words; bitmap word x = (tile column << lw) + word), one
+// brick per wave at a time.
+__device__ void flush_tile_bricks(const BrickOut &o, const uint32_t *bits, const TilePlan &p,
+                                  int32_t ti0, int32_t tj0, int32_t tk0, int lane, int wave,
+                                  int nwaves, uint32_t *status) {
+    const int32_t nbx = 1 << (p.lx - 3), nby = 1 << (p.ly - 3), nbz = 1 << p.lw;
+    const int32_t u = lane >> 3, v = lane & 7;
+    for (int32_t bi = wave; bi < nbx * nby * nbz; bi += nwaves) {
+        const int32_t bzl = bi & (nbz - 1), rest = bi >> p.lw;
+        const int32_t byl = rest & (nby - 1), bxl = rest >> (p.ly - 3);
+        const int32_t col = ((8 * bxl + u) << p.ly) + 8 * byl + v;
+        const uint32_t word = bits[(col << p.lw) + bzl];
+        const uint32_t id = ((uint32_t)((ti0 >> 3) + bxl) * (uint32_t)o.nby + (uint32_t)((tj0 >> 3) + byl)) *
+                                (uint32_t)o.nbz + (uint32_t)((tk0 >> 5) + bzl);
+        brick_merge_wave(o, id, word, lane, status);
+    }
 }
 
 // Wave-level scans (one value per lane of a 64-lane wave).
@@ -942,6 +1017,13 @@ __global__ void __launch_bounds__(kTileThreads)
         }
         __syncthreads();  // every wave done with this task's bitmap
 
+        if (T.bricks.index) {
+            // sparse output: the tile's bricks, merged per wave
+            flush_tile_bricks(T.bricks, s_bits, p, ti0, tj0, tk0, lane, wv, kTileWaves,
+                              b.status + d.mesh);
+            __syncthreads();
+            continue;
+        }
         // flush the tile: word x of the bitmap is word (x & (tw-1)) of
         // tile-local column x >> lw
         const bool shared_tile = s_shared != 0;
@@ -999,6 +1081,78 @@ __global__ void __launch_bounds__(256) k_large_tets(MeshTable T, BinBuffers b, i
                 const int64_t col = (int64_t)(lo[0] + di) * g.n[1] + (lo[1] + dj);
                 or_run_global(d.grid + col * g.words, lo[2] + s0, lo[2] + s1);
             }
+        }
+    }
+}
+
+
+// Large tets with sparse output: one workgroup per tet walks the tiles its
+// box meets; per tile it builds the tile bitmap in LDS from the box's
+// columns, then merges the tile's bricks like the tile kernel does.
+__global__ void __launch_bounds__(256) k_large_tets_bricks(MeshTable T, BinBuffers b, int strict) {
+    __shared__ uint32_t s_bits[kMaxTileWords];
+    const uint32_t nbig = b.meta[kMetaBig];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const MeshDesc &d = T.one;
+    const GridGeom g = d.g;
+    const TilePlan p = d.p;
+    const int32_t tw = 1 << p.lw, nwords = (1 << (p.lx + p.ly)) << p.lw;
+    for (uint32_t e = blockIdx.x; e < nbig; e += gridDim.x) {
+        const int4 Tt = d.tets[b.big[e] - d.tet_base];
+        const int4 *q4 = b.q4 + d.vert_base;
+        const int4 A = q4[Tt.x], B = q4[Tt.y], C = q4[Tt.z], D = q4[Tt.w];
+        int32_t lo[3], hi[3];
+        candidate_box(A, B, C, D, g, lo, hi);
+        const double p0[3] = {(double)((2 * lo[0] + 1) * g.half[0]),
+                              (double)((2 * lo[1] + 1) * g.half[1]),
+                              (double)((2 * lo[2] + 1) * g.half[2])};
+        Face f[4];
+        uint32_t lower;
+        if (!build_faces(A, B, C, D, p0, g, strict != 0, f, lower)) continue;
+        const int32_t nk = hi[2] - lo[2] + 1;
+        const double nkd = (double)nk;
+        for (int32_t tx = lo[0] >> p.lx; tx <= hi[0] >> p.lx; ++tx)
+            for (int32_t ty = lo[1] >> p.ly; ty <= hi[1] >> p.ly; ++ty)
+                for (int32_t tz = lo[2] >> (5 + p.lw); tz <= hi[2] >> (5 + p.lw); ++tz) {
+                    const int32_t ti0 = tx << p.lx, tj0 = ty << p.ly, tk0 = tz << (5 + p.lw);
+                    for (int32_t x = tid; x < nwords; x += 256) s_bits[x] = 0u;
+                    __syncthreads();
+                    // the box's columns inside this tile, z clipped to it
+                    const int32_t i0 = max(lo[0], ti0), i1 = min(hi[0], ti0 + (1 << p.lx) - 1);
+                    const int32_t j0 = max(lo[1], tj0), j1 = min(hi[1], tj0 + (1 << p.ly) - 1);
+                    const int32_t z0 = max(lo[2], tk0), z1 = min(hi[2], tk0 + (tw << 5) - 1);
+                    const int32_t nj = j1 - j0 + 1, ncols = (i1 - i0 + 1) * nj;
+                    for (int32_t c = tid; c < ncols; c += 256) {
+                        const int32_t ci = i0 + c / nj, cj = j0 + c % nj;
+                        int32_t s0, s1;
+                        column_span(f, lower, (double)(ci - lo[0]), (double)(cj - lo[1]), nk, nkd, s0, s1);
+                        s0 = max(s0 + lo[2], z0);
+                        s1 = min(s1 + lo[2], z1 + 1);
+                        if (s0 < s1)
+                            or_run_lds(s_bits + ((((ci - ti0) << p.ly) + (cj - tj0)) << p.lw), s0 - tk0,
+                                       s1 - tk0);
+                    }
+                    __syncthreads();
+                    flush_tile_bricks(T.bricks, s_bits, p, ti0, tj0, tk0, lane, wv, 4, b.status + d.mesh);
+                    __syncthreads();
+                }
+    }
+}
+
+// Sparse output, last pass: a published slot whose 64 words all came out
+// set (contributions merged after it was taken) becomes kBrickFull, so that
+// "every voxel set" has one representation.  One wave per slot.
+__global__ void __launch_bounds__(256) k_bricks_canonical(BrickOut o) {
+    const int lane = threadIdx.x & 63;
+    const int64_t nslots = min((int64_t)*o.count, o.capacity);
+    for (int64_t s = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6; s < nslots;
+         s += ((int64_t)gridDim.x * 256) >> 6) {
+        const uint32_t id = o.ids[s];
+        if (id == kBrickUnused) continue;  // the same for every lane of the wave
+        const bool full = __ballot(o.pool[(size_t)s * 64u + lane] == 0xffffffffu) == ~0ull;
+        if (full && lane == 0 && o.index[id] == (uint32_t)s + 1u) {
+            o.index[id] = kBrickFull;
+            o.ids[s] = kBrickUnused;
         }
     }
 }
@@ -1071,6 +1225,13 @@ void launch_set_word(uint32_t *p, uint32_t value, hipStream_t s) {
 template <bool kScatter>
 void launch_bin(const MeshTable &T, const BinBuffers &b, hipStream_t s) {
     if (T.nt_total <= 0) return;
+    if (T.piece_cap > kPieceCapMax) {
+        // sparse output (one mesh): one tet per thread keeps the rank table
+        // of kPieceCapBricks slots per tet within LDS
+        k_bin<kScatter, 1, false, kPieceCapBricks>
+            <<<(unsigned)blocks_for(T.nt_total, kBinThreads), kBinThreads, 0, s>>>(T, b);
+        return;
+    }
     const bool many = T.nt_total >= kBinTetsMany;
     const unsigned blocks = (unsigned)blocks_for(T.nt_total, kBinThreads * (many ? 4 : 2));
     if (T.descs) {
@@ -1106,7 +1267,13 @@ void launch_tile_voxelize(const MeshTable &T, const BinBuffers &b, bool strict, 
 
 void launch_large_tets(const MeshTable &T, const BinBuffers &b, bool strict, int workgroups,
                        hipStream_t s) {
-    k_large_tets<<<(unsigned)workgroups, 256, 0, s>>>(T, b, strict ? 1 : 0);
+    if (T.bricks.index) k_large_tets_bricks<<<(unsigned)workgroups, 256, 0, s>>>(T, b, strict ? 1 : 0);
+    else k_large_tets<<<(unsigned)workgroups, 256, 0, s>>>(T, b, strict ? 1 : 0);
+}
+
+void launch_bricks_canonical(const MeshTable &T, const BinBuffers &b, int workgroups, hipStream_t s) {
+    (void)b;
+    k_bricks_canonical<<<(unsigned)workgroups, 256, 0, s>>>(T.bricks);
 }
 
 void launch_voxelize_per_tet(const MeshDesc &d, const BinBuffers &b, bool strict, hipStream_t s) {

@@ -13,6 +13,7 @@ namespace tv {
 constexpr int32_t kMetaWords = 64;
 constexpr int32_t kMinStatusWords = 64;
 constexpr int32_t kPieceCap = 8;  // piece slots reserved per tet (the largest piece_cap)
+constexpr int32_t kPieceCapSparse = 27;  // the same for sparse-output calls
 
 // Launch parameters of the tile pipeline (tv_params in the C ABI).
 struct Params {
@@ -82,6 +83,7 @@ struct CallSizes {
     // the descriptors live in a device table inside the workspace (batch
     // calls); otherwise a single mesh's descriptor is a kernel argument
     bool table = false;
+    int32_t piece_slots = kPieceCap;  // piece slots per tet
 };
 
 struct WorkspaceLayout {
@@ -96,7 +98,7 @@ struct WorkspaceLayout {
     size_t descs;        // meshes MeshDesc, then 3 x (meshes + 1) int64 prefix sums
     size_t descs_bytes;
     size_t q4;           // nv int4 lattice vertices (.w = invalid flag)
-    size_t pieces;       // nt * kPieceCap uint32
+    size_t pieces;       // nt * piece_slots uint32
     size_t big;          // nt uint32
     size_t trec;         // nt uint2: per-tet tile summary from the counting pass
     size_t total;
@@ -133,7 +135,7 @@ inline WorkspaceLayout layout(const CallSizes &c) {
     L.q4 = off;
     off = align256(off + 16 * (size_t)c.nv);
     L.pieces = off;
-    off = align256(off + 4 * (size_t)c.nt * (size_t)kPieceCap);
+    off = align256(off + 4 * (size_t)c.nt * (size_t)c.piece_slots);
     L.big = off;
     off = align256(off + 4 * (size_t)c.nt);
     L.trec = off;

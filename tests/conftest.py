@@ -20,3 +20,12 @@ def oracle_mod():
     if not os.path.exists(oracle.LIB):
         oracle.build()
     return oracle
+
+
+@pytest.fixture(scope="session")
+def large():
+    """The large workload (128^3 cubes, 1024^3 grid), generated once per
+    session: several GPU test files use it."""
+    from paper_2106_01326_amd import synth
+
+    return synth.workload_large()

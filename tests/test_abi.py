@@ -195,3 +195,49 @@ def test_noalloc_host_checks(lib):
         tv.TV_ERR_UNSUPPORTED_DIMS
     bad = tv._bbox(((0, 0, 0), (1, 0, 1)))
     assert call(P(256), 4, P(256), 1, d, bad, P(256), None, None, 0) == tv.TV_ERR_INVALID_ARG
+
+
+def test_export_host_checks(lib):
+    """tv_export_batch refuses bad arguments before touching the device."""
+    P = ctypes.c_void_p
+    ref = (tv.GridRefC * 1)(tv.GridRefC(P(256), tv.Dims(32, 32, 32)))
+    call = lib.tv_export_batch
+    ws_n = lib.tv_export_workspace_bytes(1)
+    assert ws_n >= 256 and ws_n % 256 == 0 and lib.tv_export_workspace_bytes(0) == 0
+    a = ctypes.cast(ref, P)
+    assert call(a, 1, 12, 0, P(256), P(256), ws_n, None) == tv.TV_ERR_INVALID_ARG  # res not a power of two
+    assert call(a, 1, 2048, 0, P(256), P(256), ws_n, None) == tv.TV_ERR_INVALID_ARG
+    assert call(a, 1, 32, 5, P(256), P(256), ws_n, None) == tv.TV_ERR_INVALID_ARG  # mode
+    assert call(a, 0, 32, 0, P(256), P(256), ws_n, None) == tv.TV_ERR_INVALID_ARG
+    assert call(a, 1, 32, 0, None, P(256), ws_n, None) == tv.TV_ERR_INVALID_ARG
+    assert call(a, 1, 32, 0, P(256), P(260), ws_n, None) == tv.TV_ERR_WORKSPACE
+    assert call(a, 1, 32, 0, P(256), P(256), 16, None) == tv.TV_ERR_WORKSPACE
+    bad = (tv.GridRefC * 1)(tv.GridRefC(P(256), tv.Dims(32, 24, 32)))
+    assert call(ctypes.cast(bad, P), 1, 32, 0, P(256), P(256), ws_n, None) == tv.TV_ERR_UNSUPPORTED_DIMS
+    # pooling 1024^3 to one cell would count 2^30 voxels in a float
+    big = (tv.GridRefC * 1)(tv.GridRefC(P(256), tv.Dims(1024, 1024, 1024)))
+    assert call(ctypes.cast(big, P), 1, 1, 0, P(256), P(256), ws_n, None) == tv.TV_ERR_INVALID_ARG
+
+
+def test_bricks_voxelize_host_checks(lib):
+    """tv_voxelize_bricks refuses what the host can see: dims below one brick
+    or not powers of two, null outputs, capacity, flags, workspace."""
+    P = ctypes.c_void_p
+    box = tv._bbox(((0, 0, 0), (1, 1, 1)))
+    ws_n = lib.tv_voxelize_bricks_workspace_bytes(4, 1, tv.Dims(64, 64, 64))
+    assert ws_n > tv.workspace_bytes(4, 1, (64, 64, 64)) - 1 and ws_n % 256 == 0
+
+    def call(dims=(64, 64, 64), index=256, pool=256, ids=256, cap=16, count=256, ws=256, ws_bytes=None, flags=0):
+        return lib.tv_voxelize_bricks(P(256), 4, P(256), 1, tv.Dims(*dims), box, P(index), P(pool), P(ids), cap,
+                                      P(count), P(ws), ws_n if ws_bytes is None else ws_bytes, None, flags)
+
+    assert call(dims=(4, 64, 64)) == tv.TV_ERR_UNSUPPORTED_DIMS   # below 8 columns
+    assert call(dims=(64, 64, 16)) == tv.TV_ERR_UNSUPPORTED_DIMS  # below one word
+    assert call(dims=(64, 48, 64)) == tv.TV_ERR_UNSUPPORTED_DIMS
+    assert call(index=0) == tv.TV_ERR_INVALID_ARG
+    assert call(count=0) == tv.TV_ERR_INVALID_ARG
+    assert call(pool=0) == tv.TV_ERR_INVALID_ARG
+    assert call(cap=-1) == tv.TV_ERR_INVALID_ARG
+    assert call(flags=tv.ACCUMULATE) == tv.TV_ERR_INVALID_ARG
+    assert call(ws=0) == tv.TV_ERR_WORKSPACE
+    assert call(ws_bytes=ws_n - 256) == tv.TV_ERR_WORKSPACE

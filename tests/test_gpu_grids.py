@@ -150,3 +150,51 @@ def test_bricks_rejects_unsupported_dims():
     g = dev_words(np.zeros(4 * 8, dtype=np.uint32))
     with pytest.raises(tv.TVError):
         tv.bricks(g, (4, 8, 32))
+
+
+# ----------------------------------------------------------- batch export
+
+EXPORT_DIMS = [(32, 32, 32), (64, 64, 64), (8, 32, 64), (1, 2, 1024), (16, 16, 16), (128, 4, 32)]
+
+
+@pytest.mark.parametrize("res", [1, 8, 32, 64])
+def test_export_batch_random_grids(res):
+    import torch
+
+    import oracle.grids as G
+    import paper_2106_01326_amd as tv
+
+    banner(f"export batch res={res}")
+    rng = np.random.default_rng(res + 11)
+    ws = [rand_words(rng, d, 0.35) for d in EXPORT_DIMS]
+    items = [(dev_words(w), d) for w, d in zip(ws, EXPORT_DIMS)]
+    frac = tv.export_batch(items, res, "fraction")
+    anyv = tv.export_batch(items, res, "any")
+    torch.cuda.synchronize()
+    want_f = G.export_batch(list(zip(ws, EXPORT_DIMS)), res, 0).astype(np.float32)
+    want_a = G.export_batch(list(zip(ws, EXPORT_DIMS)), res, 1)
+    assert frac.dtype == torch.float32 and anyv.dtype == torch.uint8
+    assert np.array_equal(frac.cpu().numpy(), want_f)
+    assert np.array_equal(anyv.cpu().numpy(), want_a)
+
+
+def test_export_batch_of_a_voxelized_batch(oracle_mod):
+    """Uneven meshes voxelized in one batch call, exported at 32^3 and 16^3,
+    against the oracle's grids exported by the numpy oracle."""
+    import torch
+
+    import oracle.grids as G
+    import paper_2106_01326_amd as tv
+
+    meshes = synth.workload_batch(24, seed=31, workers=1)
+    banner(f"export of a voxelized batch of {len(meshes)} meshes")
+    items = [(torch.from_numpy(m.verts).cuda(), torch.from_numpy(m.tets).cuda(), m.dims, m.bbox, False)
+             for m in meshes]
+    grids, _ = tv.voxelize_batch(items)
+    refs = [(g, m.dims) for g, m in zip(grids, meshes)]
+    want_grids = [(oracle_mod.voxelize_mesh(m), m.dims) for m in meshes]
+    for res in (32, 16):
+        got = tv.export_batch(refs, res, "fraction")
+        torch.cuda.synchronize()
+        want = G.export_batch(want_grids, res, 0).astype(np.float32)
+        assert np.array_equal(got.cpu().numpy(), want), f"res {res}"

@@ -295,11 +295,6 @@ def medium():
     return synth.workload_medium()
 
 
-@pytest.fixture(scope="module")
-def large():
-    return synth.workload_large()
-
-
 @pytest.mark.parametrize("per_tet", [False, True])
 def test_medium_workload_full_grid(oracle_mod, medium, per_tet):
     banner(f"medium workload nt={medium.nt} nv={medium.nv} per_tet={per_tet}")
