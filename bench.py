@@ -63,13 +63,45 @@ def _memo(key, fn):
     return _MESHES[key]
 
 
+CACHE_DIR = None  # --cache-dir: single-mesh workloads saved as .npz and reused
+
+
+def _cached(name, gen):
+    """The mesh from the cache directory when it holds it, else generated
+    (and saved there).  The file name carries the workload and the seed's
+    default, and the arrays are compared with nothing: delete the directory
+    after changing the generator."""
+    from paper_2106_01326_amd import synth
+
+    if not CACHE_DIR:
+        return gen()
+    path = os.path.join(CACHE_DIR, f"{name}.npz")
+    if os.path.exists(path):
+        d = np.load(path, allow_pickle=False)
+        m = synth.Mesh(tets=d["tets"], dims=tuple(int(x) for x in d["dims"]), bbox=(d["lo"], d["hi"]),
+                       meta=json.loads(str(d["meta"])))
+        if "verts" in d.files:
+            m.verts = d["verts"]
+        else:
+            m.qverts = d["qverts"]
+        return m
+    m = gen()
+    os.makedirs(CACHE_DIR, exist_ok=True)
+    arrs = {"tets": m.tets, "dims": np.array(m.dims), "lo": m.bbox[0], "hi": m.bbox[1],
+            "meta": np.array(json.dumps(m.meta))}
+    arrs["verts" if m.verts is not None else "qverts"] = m.verts if m.verts is not None else m.qverts
+    np.savez(path + ".tmp.npz", **arrs)
+    os.replace(path + ".tmp.npz", path)
+    return m
+
+
 def make_workload(name):
     from paper_2106_01326_amd import synth
 
     gen = {"large": synth.workload_large, "medium": synth.workload_medium, "small": synth.workload_small}
     if name not in gen:
         raise SystemExit(f"unknown workload {name}")
-    return _memo(name, gen[name])
+    return _memo(name, lambda: _cached(name, gen[name]))
 
 
 def batch_meshes(count):
@@ -337,6 +369,26 @@ def batch_core(args, torch, tv, meshes, steps, warmup, cpu=True):
                             "bit_identical": bool(graph_same)},
            "stage_ms": {k: v_ / max(calls, 1) for k, v_ in stages.items()}}
     res["roofline"] = tile_roofline(torch, tv, items, meshes, stages.get("voxelize", 0.0) / max(calls, 1))
+    # the batch's grids exported to one CNN input tensor per resolution
+    exp = tv.Export([(g, m.dims) for g, m in zip(batch.grids, meshes)])
+    res["export"] = {}
+    for r_ in (32, 64):
+        out_t = torch.empty((len(meshes), r_, r_, r_), dtype=torch.float32, device=dev)
+        ws_e = tv.alloc_workspace(int(tv.load_library().tv_export_workspace_bytes(len(meshes))), dev)
+        exp.run(r_, "fraction", out=out_t, workspace=ws_e, stream=stream)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(steps):
+            exp.run(r_, "fraction", out=out_t, workspace=ws_e, stream=stream)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms_e = ev0.elapsed_time(ev1) / steps
+        in_bytes = sum(tv.grid_words(m.dims) * 4 for m in meshes)
+        res["export"][f"res{r_}_f32"] = {"ms": ms_e, "out_bytes": out_t.numel() * 4,
+                                         "GB_per_s": (in_bytes + out_t.numel() * 4) / (ms_e * 1e-3) / 1e9}
+        del out_t, ws_e
+    del exp
+    log(f"export: {res['export']}")
     if cpu:
         res["cpu_baseline"] = cpu_baseline_batch(meshes, batch, args.cpu_seconds)
     del grids, wss, items, batch
@@ -354,7 +406,7 @@ def bench_batch(args, torch, tv):
            "config": {"workload": "uneven batch of small meshes", "meshes": len(meshes), "tets": r["tets"],
                       "grids": "32^3 or 64^3", "vert_format": "f32"}}
     for k in ("tets_per_s", "per_mesh_loop", "batched_over_per_mesh", "bit_identical_to_per_mesh",
-              "graph_replay", "stage_ms", "roofline"):
+              "graph_replay", "stage_ms", "roofline", "export"):
         out[k] = r[k]
     out["cpu_baseline"] = r.get("cpu_baseline")
     print(json.dumps(out), flush=True)
@@ -942,6 +994,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="large workload only: skip the batch and serving measurements that the "
                          "default line carries next to the headline")
+    ap.add_argument("--cache-dir", default=None,
+                    help="keep the generated single-mesh workloads as .npz files here and reuse them "
+                         "(for repeated profiler passes)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="before the workload, run one plain device copy of this many MiB so "
                          "that a hardware-counter run can scale its byte counters")
@@ -952,6 +1007,8 @@ def main():
               "(multi-GPU sharding is a design note only); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    global CACHE_DIR
+    CACHE_DIR = args.cache_dir
     # every synthetic input first: nothing below may fork or spawn workers
     # once the process has touched the GPU
     pregenerate(args)
@@ -1076,7 +1133,7 @@ def main():
                        cpu=not args.no_cpu_baseline)
         out["batch"] = {k: b[k] for k in ("meshes", "tets", "ms_per_batch", "meshes_per_s", "tets_per_s",
                                           "per_mesh_loop", "batched_over_per_mesh",
-                                          "bit_identical_to_per_mesh", "graph_replay", "stage_ms")}
+                                          "bit_identical_to_per_mesh", "graph_replay", "stage_ms", "export")}
         out["batch"]["roofline_frac"] = b["roofline"]["frac"]
         if b.get("cpu_baseline"):
             out["batch"]["oracle_bit_exact_on_sample"] = b["cpu_baseline"]["gpu_bit_exact_on_sample"]

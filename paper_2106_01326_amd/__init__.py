@@ -389,36 +389,49 @@ def voxelize_noalloc(verts, tets, dims, bbox, *, strict=False, grid=None, status
     return grid, status
 
 
+class Export:
+    """The (grid, dims) list of a batch export, marshalled once
+    (tv_export_batch takes it as a host array); ``run`` exports the grids'
+    current contents.  ``grids``: list of (grid tensor, dims)."""
+
+    def __init__(self, grids):
+        torch = _torch()
+        self.n = len(grids)
+        if self.n == 0:
+            raise ValueError("no grids")
+        self.grids = list(grids)  # keeps the tensors alive
+        self.array = (GridRefC * self.n)()
+        for i, (g, dims) in enumerate(self.grids):
+            gptr, _ = _dev_ptr(g, torch.int32, None, f"grids[{i}]")
+            if g.numel() < grid_words(dims):
+                raise ValueError(f"grids[{i}] tensor too small for dims {dims}")
+            self.array[i] = GridRefC(gptr, _dims(dims))
+        self.device = self.grids[0][0].device
+
+    def run(self, res, mode="fraction", *, out=None, workspace=None, stream=None):
+        """One dense [n, res, res, res] tensor: float32 fractions
+        (``mode="fraction"``) or uint8 occupancy (``mode="any"``)."""
+        lib = load_library()
+        torch = _torch()
+        code = {"fraction": EXPORT_FRACTION, "any": EXPORT_ANY}[mode]
+        dt = torch.float32 if code == EXPORT_FRACTION else torch.uint8
+        if out is None:
+            out = torch.empty((self.n, res, res, res), dtype=dt, device=self.device)
+        optr, _ = _dev_ptr(out, dt, None, "out")
+        if out.numel() < self.n * res ** 3:
+            raise ValueError("out too small")
+        if workspace is None:
+            workspace = alloc_workspace(int(lib.tv_export_workspace_bytes(self.n)), self.device)
+        wptr, _ = _dev_ptr(workspace, torch.uint8, None, "workspace")
+        _check(lib.tv_export_batch(ctypes.cast(self.array, ctypes.c_void_p), self.n, int(res), code, optr, wptr,
+                                   workspace.numel(), _stream_handle(stream)))
+        return out
+
+
 def export_batch(grids, res, mode="fraction", *, out=None, workspace=None, stream=None):
     """Many grids of any dims -> one dense [n, res, res, res] tensor in one
-    launch (tv_export_batch): float32 fractions (``mode="fraction"``) or
-    uint8 occupancy (``mode="any"``).  ``grids``: list of (grid tensor, dims)."""
-    lib = load_library()
-    torch = _torch()
-    n = len(grids)
-    if n == 0:
-        raise ValueError("no grids")
-    code = {"fraction": EXPORT_FRACTION, "any": EXPORT_ANY}[mode]
-    arr = (GridRefC * n)()
-    for i, (g, dims) in enumerate(grids):
-        gptr, _ = _dev_ptr(g, torch.int32, None, f"grids[{i}]")
-        if g.numel() < grid_words(dims):
-            raise ValueError(f"grids[{i}] tensor too small for dims {dims}")
-        arr[i] = GridRefC(gptr, _dims(dims))
-    dev = grids[0][0].device
-    dt = torch.float32 if code == EXPORT_FRACTION else torch.uint8
-    if out is None:
-        out = torch.empty((n, res, res, res), dtype=dt, device=dev)
-    optr, _ = _dev_ptr(out, dt, None, "out")
-    if out.numel() < n * res ** 3:
-        raise ValueError("out too small")
-    need = int(lib.tv_export_workspace_bytes(n))
-    if workspace is None:
-        workspace = alloc_workspace(need, dev)
-    wptr, _ = _dev_ptr(workspace, torch.uint8, None, "workspace")
-    _check(lib.tv_export_batch(ctypes.cast(arr, ctypes.c_void_p), n, int(res), code, optr, wptr,
-                               workspace.numel(), _stream_handle(stream)))
-    return out
+    launch (tv_export_batch); see ``Export`` to marshal the list once."""
+    return Export(grids).run(res, mode, out=out, workspace=workspace, stream=stream)
 
 
 def bricks_workspace_bytes(nv: int, nt: int, dims) -> int:

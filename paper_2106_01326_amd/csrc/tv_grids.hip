@@ -276,42 +276,65 @@ struct ExportRef {
     int32_t words;
 };
 
-// One thread per output cell (grid-stride): per axis the cell's source range
-// is a block of 2^(ln - lres) voxels (pooled axis) or the single voxel it
-// repeats; the set voxels of the block are counted word by word along z.
-template <bool kFraction>
+// Set voxels of the source block of output cell c of grid g (per axis a
+// block of 2^(ln - lres) voxels on a pooled axis, the one voxel it repeats
+// otherwise), counted word by word along z; lblock = log2 of the block size.
+__device__ __forceinline__ uint32_t export_count(const ExportRef &g, const int32_t c[3], int32_t lres,
+                                                 int32_t &lblock) {
+    int32_t lo[3], len[3];
+    lblock = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int32_t d = g.ln[a] - lres;
+        lo[a] = d >= 0 ? c[a] << d : c[a] >> -d;
+        len[a] = d >= 0 ? 1 << d : 1;
+        lblock += d >= 0 ? d : 0;
+    }
+    const int32_t k0 = lo[2], k1 = lo[2] + len[2] - 1, w0 = k0 >> 5, w1 = k1 >> 5;
+    uint32_t cnt = 0;
+    for (int32_t i = lo[0]; i < lo[0] + len[0]; ++i)
+        for (int32_t j = lo[1]; j < lo[1] + len[1]; ++j) {
+            const uint32_t *col = g.grid + (((int64_t)i << g.ln[1]) + j) * g.words;
+            for (int32_t w = w0; w <= w1; ++w) {
+                uint32_t m = 0xffffffffu;
+                if (w == w0) m &= 0xffffffffu << (k0 & 31);
+                if (w == w1) m &= 0xffffffffu >> (31 - (k1 & 31));
+                cnt += (uint32_t)__popc(col[w] & m);
+            }
+        }
+    return cnt;
+}
+
+// One thread per V consecutive output cells along z (grid-stride; V = 4
+// when res is a multiple of 4, so a thread writes one float4 or 4 bytes).
+// A block holds at most 2^24 voxels, so the count and the fraction
+// (count * 2^-lblock) are exact in float.
+template <bool kFraction, int V>
 __global__ void __launch_bounds__(kThreads)
     k_export(const ExportRef *__restrict__ tab, int64_t total, int32_t lres, void *__restrict__ out) {
     const int64_t stride = (int64_t)gridDim.x * kThreads;
     const int32_t cmask = (1 << lres) - 1;
-    for (int64_t o = (int64_t)blockIdx.x * kThreads + threadIdx.x; o < total; o += stride) {
+    for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < total / V; t += stride) {
+        const int64_t o = t * V;
         const ExportRef g = tab[o >> (3 * lres)];
-        const int32_t c[3] = {(int32_t)(o >> (2 * lres)) & cmask, (int32_t)(o >> lres) & cmask,
-                              (int32_t)o & cmask};
-        int32_t lo[3], len[3], lblock = 0;
+        int32_t c[3] = {(int32_t)(o >> (2 * lres)) & cmask, (int32_t)(o >> lres) & cmask, (int32_t)o & cmask};
+        float f[V];
+        uint32_t any = 0;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const int32_t d = g.ln[a] - lres;
-            lo[a] = d >= 0 ? c[a] << d : c[a] >> -d;
-            len[a] = d >= 0 ? 1 << d : 1;
-            lblock += d >= 0 ? d : 0;
+        for (int q = 0; q < V; ++q) {
+            int32_t lblock;
+            const uint32_t cnt = export_count(g, c, lres, lblock);
+            f[q] = ldexpf((float)cnt, -lblock);
+            any |= (cnt ? 1u : 0u) << (8 * q);
+            ++c[2];
         }
-        const int32_t k0 = lo[2], k1 = lo[2] + len[2] - 1, w0 = k0 >> 5, w1 = k1 >> 5;
-        uint32_t cnt = 0;
-        for (int32_t i = lo[0]; i < lo[0] + len[0]; ++i)
-            for (int32_t j = lo[1]; j < lo[1] + len[1]; ++j) {
-                const uint32_t *col = g.grid + (((int64_t)i << g.ln[1]) + j) * g.words;
-                for (int32_t w = w0; w <= w1; ++w) {
-                    uint32_t m = 0xffffffffu;
-                    if (w == w0) m &= 0xffffffffu << (k0 & 31);
-                    if (w == w1) m &= 0xffffffffu >> (31 - (k1 & 31));
-                    cnt += (uint32_t)__popc(col[w] & m);
-                }
-            }
-        // a block holds at most 2^24 voxels, so the count and the fraction
-        // (count * 2^-lblock) are exact in float
-        if (kFraction) static_cast<float *>(out)[o] = ldexpf((float)cnt, -lblock);
-        else static_cast<uint8_t *>(out)[o] = cnt ? 1 : 0;
+        if (V == 4) {
+            if (kFraction) reinterpret_cast<float4 *>(out)[t] = make_float4(f[0], f[1], f[2], f[3]);
+            else reinterpret_cast<uint32_t *>(out)[t] = any;
+        } else {
+            if (kFraction) static_cast<float *>(out)[o] = f[0];
+            else static_cast<uint8_t *>(out)[o] = (uint8_t)any;
+        }
     }
 }
 
@@ -463,11 +486,20 @@ tv_status tv_export_batch(const tv_grid_ref *grids, int32_t n, int32_t res, uint
     if (hipMemcpyAsync(ws, tab.data(), sizeof(ExportRef) * tab.size(), hipMemcpyHostToDevice, s) != hipSuccess)
         return tv::set_error(TV_ERR_HIP, "export: table upload failed");
     const int64_t total = (int64_t)n << (3 * lres);
-    const int64_t want = (total + kThreads - 1) / kThreads;
-    const unsigned blocks = (unsigned)(want < 65536 ? want : 65536);
     const ExportRef *dtab = static_cast<const ExportRef *>(ws);
-    if (mode == TV_EXPORT_FRACTION) k_export<true><<<blocks, kThreads, 0, s>>>(dtab, total, lres, out);
-    else k_export<false><<<blocks, kThreads, 0, s>>>(dtab, total, lres, out);
+    // four cells per thread when they stay within one output row and the
+    // output is aligned for a 16-byte (float) or 4-byte (uint8) store
+    const bool vec4 = res >= 4 &&
+                      (reinterpret_cast<uintptr_t>(out) & (mode == TV_EXPORT_FRACTION ? 15u : 3u)) == 0;
+    const int64_t want = (total / (vec4 ? 4 : 1) + kThreads - 1) / kThreads;
+    const unsigned blocks = (unsigned)(want < 65536 ? want : 65536);
+    if (mode == TV_EXPORT_FRACTION) {
+        if (vec4) k_export<true, 4><<<blocks, kThreads, 0, s>>>(dtab, total, lres, out);
+        else k_export<true, 1><<<blocks, kThreads, 0, s>>>(dtab, total, lres, out);
+    } else {
+        if (vec4) k_export<false, 4><<<blocks, kThreads, 0, s>>>(dtab, total, lres, out);
+        else k_export<false, 1><<<blocks, kThreads, 0, s>>>(dtab, total, lres, out);
+    }
     return launched("export launch");
 }
 

@@ -281,8 +281,9 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(MeshTable T, BinBuffers b) 
         sys[u] = (uint32_t)d.p.ntz;
         sxs[u] = (uint32_t)d.p.nty * sys[u];
         if (d.direct) {
-            // a single-tile grid: every tet is a piece of tile 0, in tet
-            // order, so the count is the tet count and nothing is scattered
+            // a single-tile grid: every tet is a piece of its one tile, in
+            // tet order, so the count is the tet count and nothing is
+            // scattered (the tile kernel checks these tets' indices)
             if (!kScatter && t == d.tet_base) b.tile_count[d.tile_base] = (uint32_t)d.nt;
         } else if (!kScatter) {
             TileRange r = {0, -1, 0, -1, 0, -1};
@@ -672,6 +673,56 @@ __device__ void flush_tile_bricks(const BrickOut &o, const uint32_t *bits, const
     }
 }
 
+// The tile kernel's flush of a tile's bricks under sparse output, where
+// every tile is one task and runs before any other writer: no brick of the
+// tile has been touched, so nothing is read back or raced for.  Each wave
+// classifies its bricks (at most 16), reserves pool slots for its partly
+// filled ones with one atomic, then stores words, ids and index entries.
+__device__ void flush_fresh_tile_bricks(const BrickOut &o, const uint32_t *bits, const TilePlan &p,
+                                        int32_t ti0, int32_t tj0, int32_t tk0, int lane, int wave,
+                                        int nwaves, uint32_t *status) {
+    const int32_t nby = 1 << (p.ly - 3), nbz = 1 << p.lw;
+    const int32_t nbt = (1 << (p.lx - 3)) * nby * nbz;
+    const int32_t u = lane >> 3, v = lane & 7;
+    auto brick = [&](int32_t bi, uint32_t &id) {
+        const int32_t bzl = bi & (nbz - 1), rest = bi >> p.lw;
+        const int32_t byl = rest & (nby - 1), bxl = rest >> (p.ly - 3);
+        id = ((uint32_t)((ti0 >> 3) + bxl) * (uint32_t)o.nby + (uint32_t)((tj0 >> 3) + byl)) * (uint32_t)o.nbz +
+             (uint32_t)((tk0 >> 5) + bzl);
+        return bits[((((8 * bxl + u) << p.ly) + 8 * byl + v) << p.lw) + bzl];
+    };
+    uint32_t full = 0, mixed = 0, id;
+    for (int32_t bi = wave, k = 0; bi < nbt; bi += nwaves, ++k) {
+        const uint32_t w = brick(bi, id);
+        if (__ballot(w != 0u) == 0ull) continue;
+        if (__ballot(w == 0xffffffffu) == ~0ull) full |= 1u << k;
+        else mixed |= 1u << k;
+    }
+    uint32_t base = 0;
+    if (mixed) {
+        if (lane == 0) base = atomicAdd(o.count, (uint32_t)__popc(mixed));
+        base = __shfl(base, 0);
+    }
+    for (int32_t bi = wave, k = 0; bi < nbt; bi += nwaves, ++k) {
+        if (!(((full | mixed) >> k) & 1u)) continue;
+        const uint32_t w = brick(bi, id);
+        if ((full >> k) & 1u) {
+            if (lane == 0) o.index[id] = kBrickFull;
+            continue;
+        }
+        const uint32_t slot = base + (uint32_t)__popc(mixed & ((1u << k) - 1u));
+        if ((int64_t)slot >= o.capacity) {
+            if (lane == 0) atomicOr(status, kStatusFull);
+            continue;
+        }
+        o.pool[(size_t)slot * 64u + lane] = w;
+        if (lane == 0) {
+            o.ids[slot] = id;
+            o.index[id] = slot + 1u;
+        }
+    }
+}
+
 // Wave-level scans (one value per lane of a 64-lane wave).
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane) {
 #pragma unroll
@@ -763,12 +814,18 @@ __global__ void __launch_bounds__(kTileThreads)
         const gptr<uint32_t> pieces = as_global(b.pieces);
         const uint32_t tbase = (uint32_t)d.tet_base;
         // the mesh-local tet of piece slot x: binned pieces hold global tet
-        // ids; a single-tile grid's pieces are its tets in order (unbinned,
-        // so their indices are checked here)
+        // ids; a single-tile grid's pieces are its tets in order, unbinned,
+        // so only there are the indices and vertices checked here
         const bool direct = d.direct != 0;
         const uint32_t pbase = s_pbase;
         const int64_t nv = d.nv;
         auto tet_of = [&](uint32_t x) -> uint32_t { return direct ? x - pbase : pieces[x] - tbase; };
+        auto tet_ok = [&](int4 &Tt) {
+            if (!direct) return true;
+            const bool ok = index_ok(Tt.x, nv) && index_ok(Tt.y, nv) && index_ok(Tt.z, nv) && index_ok(Tt.w, nv);
+            if (!ok) Tt = make_int4(0, 0, 0, 0);  // gathered, never used
+            return ok;
+        };
         const int32_t tw = 1 << p.lw;
         const int32_t nwords = (1 << (p.lx + p.ly)) * tw;
         for (int32_t x = tid; x < nwords; x += kTileThreads) s_bits[x] = 0u;
@@ -788,8 +845,7 @@ __global__ void __launch_bounds__(kTileThreads)
         bool idx_ok = true;  // the prefetched tet's indices are in range
         if (pb + lane < rend) {
             int4 Tt = load_int4(tets, tet_of(pb + lane));
-            idx_ok = index_ok(Tt.x, nv) && index_ok(Tt.y, nv) && index_ok(Tt.z, nv) && index_ok(Tt.w, nv);
-            if (!idx_ok) Tt = make_int4(0, 0, 0, 0);
+            idx_ok = tet_ok(Tt);
             Vn[0] = load_int4(q4, Tt.x);
             Vn[1] = load_int4(q4, Tt.y);
             Vn[2] = load_int4(q4, Tt.z);
@@ -801,10 +857,10 @@ __global__ void __launch_bounds__(kTileThreads)
             int32_t lo[3] = {0, 0, 0}, hi[3] = {-1, -1, -1};
             int4 Vt[4];
             uint32_t nrows = 0;
-            if (pi < rend && !idx_ok) atomicOr(b.status + d.mesh, kStatusIndex);
+            if (direct && pi < rend && !idx_ok) atomicOr(b.status + d.mesh, kStatusIndex);
             // a vertex that failed ingest voids its tets (its mesh's status
-            // was raised there)
-            if (pi < rend && idx_ok && (Vn[0].w | Vn[1].w | Vn[2].w | Vn[3].w) == 0) {
+            // was raised there; binned tets were checked when binned)
+            if (pi < rend && idx_ok && (!direct || (Vn[0].w | Vn[1].w | Vn[2].w | Vn[3].w) == 0)) {
                 const int4 A = Vn[0], B = Vn[1], C = Vn[2], D = Vn[3];
                 Vt[0] = A;
                 Vt[1] = B;
@@ -901,8 +957,7 @@ __global__ void __launch_bounds__(kTileThreads)
             }
             // keeps the use of the tet record (and so its wait) after phase 1c
             asm volatile("" : "+v"(Tn.x), "+v"(Tn.y), "+v"(Tn.z), "+v"(Tn.w));
-            idx_ok = index_ok(Tn.x, nv) && index_ok(Tn.y, nv) && index_ok(Tn.z, nv) && index_ok(Tn.w, nv);
-            if (!idx_ok) Tn = make_int4(0, 0, 0, 0);
+            idx_ok = tet_ok(Tn);
             if (pn < nend) {
                 Vn[0] = load_int4(q4, Tn.x);
                 Vn[1] = load_int4(q4, Tn.y);
@@ -1018,9 +1073,10 @@ __global__ void __launch_bounds__(kTileThreads)
         __syncthreads();  // every wave done with this task's bitmap
 
         if (T.bricks.index) {
-            // sparse output: the tile's bricks, merged per wave
-            flush_tile_bricks(T.bricks, s_bits, p, ti0, tj0, tk0, lane, wv, kTileWaves,
-                              b.status + d.mesh);
+            // sparse output: the tile's bricks (this task is the tile's only
+            // one, and the large tets come after)
+            flush_fresh_tile_bricks(T.bricks, s_bits, p, ti0, tj0, tk0, lane, wv, kTileWaves,
+                                    b.status + d.mesh);
             __syncthreads();
             continue;
         }

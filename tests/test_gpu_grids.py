@@ -198,3 +198,28 @@ def test_export_batch_of_a_voxelized_batch(oracle_mod):
         torch.cuda.synchronize()
         want = G.export_batch(want_grids, res, 0).astype(np.float32)
         assert np.array_equal(got.cpu().numpy(), want), f"res {res}"
+
+
+def test_export_batch_unaligned_output():
+    """An output that is not aligned for the 4-cells-per-thread stores takes
+    the one-cell path; the values are the same."""
+    import torch
+
+    import oracle.grids as G
+    import paper_2106_01326_amd as tv
+
+    banner("export unaligned output")
+    rng = np.random.default_rng(5)
+    dims = [(32, 32, 32), (64, 16, 8)]
+    ws = [rand_words(rng, d, 0.5) for d in dims]
+    items = [(dev_words(w), d) for w, d in zip(ws, dims)]
+    res = 16
+    n = len(dims) * res ** 3
+    for mode, dt, code in (("fraction", torch.float32, 0), ("any", torch.uint8, 1)):
+        raw = torch.zeros(n + 1, dtype=dt, device="cuda")
+        tv.export_batch(items, res, mode, out=raw[1:])
+        torch.cuda.synchronize()
+        want = G.export_batch(list(zip(ws, dims)), res, code)
+        want = want.astype(np.float32) if code == 0 else want
+        assert np.array_equal(raw[1:].cpu().numpy().reshape(want.shape), want), mode
+        assert float(raw[0]) == 0
