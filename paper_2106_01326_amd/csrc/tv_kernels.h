@@ -93,6 +93,8 @@ struct BinBuffers {
     uint32_t *tile_off;     // [ntiles + 1] first piece slot per tile
     uint32_t *chunk_off;    // [ntiles + 1] first chunk of the tile of each rank
     uint32_t *tile_order;   // [ntiles] tile of each rank (largest tiles first)
+    uint32_t *rank_mesh;    // [ntiles] mesh of the tile of each rank
+    uint32_t *task_rank;    // [tasks] rank of the tile of each queue task
     uint32_t *pieces;       // [nt * piece_cap] global tet ids sorted by tile
     uint32_t *big;          // [nt] large tets (global ids)
     uint2 *trec;            // [nt] tile summary: (first tile key, shape code; 0 = no pieces)

@@ -459,6 +459,14 @@ __global__ void __launch_bounds__(1024) k_scan_tiles(MeshTable T, BinBuffers b) 
         b.chunk_off[nt] = carry;
         b.meta[kMetaChunks] = carry;
     }
+    __syncthreads();  // every chunk offset is final
+    // the task table: the rank (and mesh) behind each queue task, so that a
+    // workgroup takes a task with one lookup instead of a search
+    for (uint32_t r = tid; r < nt; r += 1024) {
+        const uint32_t t = b.tile_order[r];
+        b.rank_mesh[r] = T.n == 1 ? 0u : (uint32_t)find_mesh(T.tile_pre, T.n, (int64_t)t);
+        for (uint32_t c = b.chunk_off[r]; c < b.chunk_off[r + 1]; ++c) b.task_rank[c] = r;
+    }
 }
 
 // Tile origin (voxel indices) of local tile `lt` of a mesh.
@@ -783,13 +791,7 @@ __global__ void __launch_bounds__(kTileThreads)
             const uint32_t c = atomicAdd(&b.meta[kMetaQueue], 1u);
             s_chunk = c;
             if (c < total) {
-                // rank = last r with chunk_off[r] <= c
-                uint32_t lo = 0, hi = (uint32_t)T.ntiles_total;  // chunk_off[lo] <= c < chunk_off[hi]
-                while (hi - lo > 1) {
-                    const uint32_t mid = (lo + hi) >> 1;
-                    if (b.chunk_off[mid] <= c) lo = mid;
-                    else hi = mid;
-                }
+                const uint32_t lo = b.task_rank[c];  // the rank of the task's tile
                 const uint32_t k = c - b.chunk_off[lo];
                 const uint32_t nchunks = b.chunk_off[lo + 1] - b.chunk_off[lo];
                 const uint32_t tile = b.tile_order[lo];
@@ -800,7 +802,7 @@ __global__ void __launch_bounds__(kTileThreads)
                 s_next = s_p0;
                 s_pbase = pb;
                 s_shared = nchunks > 1 ? 1u : 0u;
-                s_mesh = T.n == 1 ? 0 : find_mesh(T.tile_pre, T.n, (int64_t)tile);
+                s_mesh = (int32_t)b.rank_mesh[lo];
             }
         }
         __syncthreads();

@@ -95,6 +95,8 @@ struct WorkspaceLayout {
     size_t tile_off;     // ntiles + 1
     size_t chunk_off;    // ntiles + 1
     size_t tile_order;   // ntiles
+    size_t rank_mesh;    // ntiles
+    size_t task_rank;    // max_tasks(c)
     size_t descs;        // meshes MeshDesc, then 3 x (meshes + 1) int64 prefix sums
     size_t descs_bytes;
     size_t q4;           // nv int4 lattice vertices (.w = invalid flag)
@@ -103,6 +105,13 @@ struct WorkspaceLayout {
     size_t trec;         // nt uint2: per-tet tile summary from the counting pass
     size_t total;
 };
+
+// Queue tasks of a call, at most: a tile has max(1, ceil(pieces / chunk))
+// of them, pieces are at most piece_slots per tet and a task holds at least
+// 64 pieces (the smallest chunk_pieces).
+inline int64_t max_tasks(const CallSizes &c) {
+    return c.ntiles + (c.nt * (int64_t)c.piece_slots + 63) / 64 + 1;
+}
 
 inline int64_t status_words(int64_t meshes) {
     return meshes > kMinStatusWords ? meshes : kMinStatusWords;
@@ -127,6 +136,10 @@ inline WorkspaceLayout layout(const CallSizes &c) {
     off = align256(off + 4 * ((size_t)c.ntiles + 1));
     L.tile_order = off;
     off = align256(off + 4 * (size_t)c.ntiles);
+    L.rank_mesh = off;
+    off = align256(off + 4 * (size_t)c.ntiles);
+    L.task_rank = off;
+    off = align256(off + 4 * (size_t)max_tasks(c));
     L.descs = off;
     L.descs_bytes = c.table ? sizeof(MeshDesc) * (size_t)c.meshes +
                                   3 * sizeof(int64_t) * ((size_t)c.meshes + 1)
@@ -153,6 +166,8 @@ inline BinBuffers bin_buffers(uint8_t *ws, const WorkspaceLayout &L) {
     b.tile_off = reinterpret_cast<uint32_t *>(ws + L.tile_off);
     b.chunk_off = reinterpret_cast<uint32_t *>(ws + L.chunk_off);
     b.tile_order = reinterpret_cast<uint32_t *>(ws + L.tile_order);
+    b.rank_mesh = reinterpret_cast<uint32_t *>(ws + L.rank_mesh);
+    b.task_rank = reinterpret_cast<uint32_t *>(ws + L.task_rank);
     b.pieces = reinterpret_cast<uint32_t *>(ws + L.pieces);
     b.big = reinterpret_cast<uint32_t *>(ws + L.big);
     b.trec = reinterpret_cast<uint2 *>(ws + L.trec);
