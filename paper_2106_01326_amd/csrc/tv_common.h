@@ -111,18 +111,27 @@ __device__ __forceinline__ bool build_faces(const int4 &A, const int4 &B, const 
                             {(double)D.x, (double)D.y, (double)D.z}};
     // (opposite vertex, three face vertices)
     const int tri[4][4] = {{0, 1, 2, 3}, {1, 0, 2, 3}, {2, 0, 1, 3}, {3, 0, 1, 2}};
+    // The side of X relative to face (U,V,W) is det[V-U, W-U, X-U], the
+    // orientation of (U,V,W,X): an alternating function of the four points,
+    // so every face's side is +-vol with vol = orientation(0,1,2,3), the sign
+    // given by the parity of (U,V,W,X) as a permutation of (0,1,2,3): odd
+    // for faces 0 and 2, even for faces 1 and 3.  vol is exact (below 2^53).
+    const double d1[3] = {v[1][0] - v[0][0], v[1][1] - v[0][1], v[1][2] - v[0][2]};
+    const double d2[3] = {v[2][0] - v[0][0], v[2][1] - v[0][1], v[2][2] - v[0][2]};
+    const double d3[3] = {v[3][0] - v[0][0], v[3][1] - v[0][1], v[3][2] - v[0][2]};
+    const double vol = (d1[1] * d2[2] - d1[2] * d2[1]) * d3[0] + (d1[2] * d2[0] - d1[0] * d2[2]) * d3[1] +
+                       (d1[0] * d2[1] - d1[1] * d2[0]) * d3[2];
+    if (vol == 0.0) return false;
+    const double oD = vol < 0.0 ? -1.0 : 1.0;
     lower_mask = 0;
 #pragma unroll
     for (int fi = 0; fi < 4; ++fi) {
-        const double *X = v[tri[fi][0]], *U = v[tri[fi][1]], *V = v[tri[fi][2]],
-                     *Wv = v[tri[fi][3]];
+        const double *U = v[tri[fi][1]], *V = v[tri[fi][2]], *Wv = v[tri[fi][3]];
         const double e1[3] = {V[0] - U[0], V[1] - U[1], V[2] - U[2]};
         const double e2[3] = {Wv[0] - U[0], Wv[1] - U[1], Wv[2] - U[2]};
         double n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
                        e1[0] * e2[1] - e1[1] * e2[0]};
-        const double side = n[0] * (X[0] - U[0]) + n[1] * (X[1] - U[1]) + n[2] * (X[2] - U[2]);
-        if (side == 0.0) return false;
-        const double o = side < 0.0 ? -1.0 : 1.0;
+        const double o = (fi & 1) ? oD : -oD;
         n[0] *= o;
         n[1] *= o;
         n[2] *= o;

@@ -261,7 +261,10 @@ template <bool kScatter, int kBinTets, bool kTable, int kCap = kPieceCapMax>
 __global__ void __launch_bounds__(kBinThreads) k_bin(MeshTable T, BinBuffers b) {
     __shared__ uint32_t s_key[kHashSlots];
     __shared__ uint32_t s_cnt[kHashSlots];  // count, then (pass 2) global slot base
-    __shared__ uint32_t s_ref[kBinTets * kBinThreads * kCap];  // slot << 16 | rank, or kNoSlot
+    // a batch call's pieces past the first kRef of a tet take their own
+    // global atomic (a smaller table here lets more workgroups share a CU)
+    constexpr int kRef = (kCap == kPieceCapMax && kTable) ? 4 : kCap;
+    __shared__ uint32_t s_ref[kBinTets * kBinThreads * kRef];  // slot << 16 | rank, or kNoSlot
     __shared__ int32_t s_bracket[2];
     const int tid = threadIdx.x;
     for (int i = tid; i < kHashSlots; i += kBinThreads) {
@@ -336,11 +339,20 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(MeshTable T, BinBuffers b) 
 #pragma unroll
     for (int u = 0; u < kBinTets; ++u) {
         const int64_t t = first + u * kBinThreads + tid;
+        // the tiles of the range in (x, y, z) order, z fastest, without divisions
+        int32_t dy = 0, dz = 0;
+        uint32_t krow = key0s[u];  // key of tile (dx, dy, 0)
         for (int32_t k = 0; k < np[u]; ++k) {
-            const int32_t dz = k % nzs[u], rest = k / nzs[u];
-            const int32_t dy = rest % nys[u], dx = rest / nys[u];
-            const uint32_t key = key0s[u] + (uint32_t)dx * sxs[u] + (uint32_t)dy * sys[u] + (uint32_t)dz;
-            const uint32_t h = hash_insert(s_key, key);
+            const uint32_t key = krow + (uint32_t)dz;
+            if (++dz == nzs[u]) {
+                dz = 0;
+                krow += sys[u];
+                if (++dy == nys[u]) {
+                    dy = 0;
+                    krow += sxs[u] - (uint32_t)nys[u] * sys[u];
+                }
+            }
+            const uint32_t h = (kScatter && k >= kRef) ? kNoSlot : hash_insert(s_key, key);
             if (!kScatter) {
                 // counts only: the ranks are the scatter pass's business
                 if (h != kNoSlot) atomicAdd(s_cnt + h, 1u);
@@ -352,7 +364,7 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(MeshTable T, BinBuffers b) 
                 ref = (h << 16) | atomicAdd(s_cnt + h, 1u);
             else
                 b.pieces[b.tile_off[key] + atomicAdd(b.tile_cursor + key, 1u)] = (uint32_t)t;
-            s_ref[(u * kBinThreads + tid) * kCap + k] = ref;
+            if (k < kRef) s_ref[(u * kBinThreads + tid) * kRef + k] = ref;
         }
     }
     __syncthreads();
@@ -367,8 +379,8 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(MeshTable T, BinBuffers b) 
 #pragma unroll
     for (int u = 0; u < kBinTets; ++u) {
         const int64_t t = first + u * kBinThreads + tid;
-        for (int32_t k = 0; k < np[u]; ++k) {
-            const uint32_t ref = s_ref[(u * kBinThreads + tid) * kCap + k];
+        for (int32_t k = 0; k < min(np[u], kRef); ++k) {
+            const uint32_t ref = s_ref[(u * kBinThreads + tid) * kRef + k];
             if (ref != kNoSlot) b.pieces[s_cnt[ref >> 16] + (ref & 0xffffu)] = (uint32_t)t;
         }
     }
@@ -781,6 +793,10 @@ __global__ void __launch_bounds__(kTileThreads)
 
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const uint32_t strip = (uint32_t)T.strip;
+    // ceil(c / strip) as one high multiply: floor(x / strip) = mulhi(x, m)
+    // with m = floor((2^32 - 1) / strip) + 1 (strip >= 2), exact for
+    // x < 2^32 / strip^2 (here x < 2^11: a piece's kept columns plus strip - 1)
+    const uint32_t strip_m = strip > 1u ? 0xffffffffu / strip + 1u : 0u;
     const uint32_t total = b.meta[kMetaChunks];
     PieceRec *const rec = s_rec[wv];
     uint32_t *const rows = s_row[wv];
@@ -955,7 +971,7 @@ __global__ void __launch_bounds__(kTileThreads)
                 R.ni = (int16_t)kept;
                 R.row0 = (uint16_t)base;
                 R.ncols = (uint16_t)prefix;
-                nstrips = (prefix + strip - 1) / strip;
+                nstrips = strip > 1u ? __umulhi(prefix + strip - 1, strip_m) : prefix;
             }
             // keeps the use of the tet record (and so its wait) after phase 1c
             asm volatile("" : "+v"(Tn.x), "+v"(Tn.y), "+v"(Tn.z), "+v"(Tn.w));
