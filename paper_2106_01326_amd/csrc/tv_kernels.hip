@@ -267,10 +267,6 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(MeshTable T, BinBuffers b) 
     __shared__ uint32_t s_ref[kBinTets * kBinThreads * kRef];  // slot << 16 | rank, or kNoSlot
     __shared__ int32_t s_bracket[2];
     const int tid = threadIdx.x;
-    for (int i = tid; i < kHashSlots; i += kBinThreads) {
-        s_key[i] = kEmptyKey;
-        s_cnt[i] = 0u;
-    }
     // each thread takes kBinTets tets, kBinThreads apart (coalesced): first
     // all their tile ranges (independent gathers in flight together), then
     // their pieces into the table
@@ -279,6 +275,18 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(MeshTable T, BinBuffers b) 
     int32_t np[kBinTets], nys[kBinTets], nzs[kBinTets];
     uint32_t key0s[kBinTets], sys[kBinTets], sxs[kBinTets];
     mesh_bracket(T, T.tet_pre, first, last, s_bracket);
+    if (kTable && T.n > 1 && s_bracket[0] == s_bracket[1]) {
+        // a workgroup inside one single-tile grid has nothing to bin
+        const MeshDesc &d0 = T.descs[s_bracket[0]];
+        if (d0.direct) {
+            if (!kScatter && tid == 0 && d0.tet_base == first) b.tile_count[d0.tile_base] = (uint32_t)d0.nt;
+            return;
+        }
+    }
+    for (int i = tid; i < kHashSlots; i += kBinThreads) {
+        s_key[i] = kEmptyKey;
+        s_cnt[i] = 0u;
+    }
     // the tile summary of this thread's tet slot u (tet t of mesh d)
     auto tile_summary = [&](int u, int64_t t, const MeshDesc &d) {
         sys[u] = (uint32_t)d.p.ntz;
