@@ -189,14 +189,17 @@ __device__ __forceinline__ void or_run_global(uint32_t *col, int32_t k_lo, int32
     }
 }
 
-// Same for a word array in LDS.
+// Same for a word array in LDS, written for the common run inside one
+// word: the first word unconditionally, whole words between, the last word
+// when it is another.
 __device__ __forceinline__ void or_run_lds(uint32_t *col, int32_t k_lo, int32_t k_hi) {
     const int32_t w0 = k_lo >> 5, w1 = (k_hi - 1) >> 5;
-    for (int32_t w = w0; w <= w1; ++w) {
-        uint32_t m = 0xffffffffu;
-        if (w == w0) m &= 0xffffffffu << (k_lo & 31);
-        if (w == w1) m &= 0xffffffffu >> (31 - ((k_hi - 1) & 31));
-        atomicOr(col + w, m);
+    const uint32_t mlo = 0xffffffffu << (k_lo & 31);
+    const uint32_t mhi = 0xffffffffu >> (31 - ((k_hi - 1) & 31));
+    atomicOr(col + w0, w0 == w1 ? mlo & mhi : mlo);
+    if (w1 > w0) {
+        for (int32_t w = w0 + 1; w < w1; ++w) atomicOr(col + w, 0xffffffffu);
+        atomicOr(col + w1, mhi);
     }
 }
 

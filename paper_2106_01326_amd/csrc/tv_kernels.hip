@@ -794,7 +794,9 @@ __global__ void __launch_bounds__(kTileThreads)
     __shared__ uint32_t s_bits[kMaxTileWords];
     __shared__ PieceRec s_rec[kTileWaves][kWaveBatch];
     // non-empty rows: j0 (8 bits) | count (8 bits) | di (6 bits) | prefix (10 bits)
-    __shared__ uint32_t s_row[kTileWaves][kRowPool];
+    // (one entry more per wave: the column loop reads the entry after the
+    // current one unconditionally)
+    __shared__ uint32_t s_row[kTileWaves][kRowPool + 1];
     __shared__ uint32_t s_soff[kTileWaves][kWaveBatch + 1];
     __shared__ uint32_t s_chunk, s_tile, s_p0, s_p1, s_shared, s_next, s_pbase;
     __shared__ int32_t s_mesh;
@@ -1059,7 +1061,7 @@ __global__ void __launch_bounds__(kTileThreads)
                     for (uint32_t c = c0; c < c1; ++c) {
                         // the next row entry, read one column ahead (used only on a
                         // row change, which happens only while columns remain)
-                        const uint32_t nx = rows[min(r + 1, (uint32_t)kRowPool - 1)];
+                        const uint32_t nx = rows[r + 1];
                         const double ddi = (double)di, ddj = (double)dj;
                         int32_t tl[4], tu[4];
 #pragma unroll
