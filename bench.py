@@ -154,7 +154,8 @@ def pregenerate(args):
         make_workload(w)
         if w == "large" and not args.no_extras:
             batch_meshes(args.batch_meshes)
-            serving_pool()
+            if args.with_serving:
+                serving_pool()
     elif w == "batch":
         batch_meshes(args.batch_meshes)
     elif w == "serving":
@@ -1009,9 +1010,11 @@ def main():
     ap.add_argument("--batch-meshes", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--with-serving", action="store_true",
+                    help="large workload: also run the serving measurement in the default line")
     ap.add_argument("--no-extras", action="store_true",
-                    help="large workload only: skip the batch and serving measurements that the "
-                         "default line carries next to the headline")
+                    help="large workload only: skip the batch measurement (and the serving one, "
+                         "with --with-serving) that the default line carries next to the headline")
     ap.add_argument("--cache-dir", default=None,
                     help="keep the generated single-mesh workloads as .npz files here and reuse them "
                          "(for repeated profiler passes)")
@@ -1156,10 +1159,15 @@ def main():
         if b.get("cpu_baseline"):
             out["batch"]["oracle_bit_exact_on_sample"] = b["cpu_baseline"]["gpu_bit_exact_on_sample"]
             out["batch"]["cpu_baseline"] = b["cpu_baseline"]
-        log("serving workload (Poisson arrivals)")
-        torch.cuda.empty_cache()
-        sv = serving_core(args, torch, tv, serving_pool())
-        out["serving"] = sv
+        if args.with_serving:
+            log("serving workload (Poisson arrivals)")
+            torch.cuda.empty_cache()
+            sv = serving_core(args, torch, tv, serving_pool())
+            out["serving"] = sv
+        else:
+            out["serving"] = None
+            out["serving_note"] = ("not in the default line: the serving percentiles come from "
+                                   "--workload serving (or --with-serving)")
     print(json.dumps(out), flush=True)
 
 
