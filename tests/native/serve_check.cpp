@@ -87,6 +87,65 @@ struct FakeExec final : tv::serve::Executor {
     }
 };
 
+// Every arena region a wave's device work would touch (its workspace, its
+// requests' input copies and grids) must be disjoint from the regions of
+// every other wave in flight and from the grids that clients still hold.
+// Regions are taken at launch and given back at finish (workspace, inputs)
+// or by the client before it releases a request (grid).
+struct RegionExec final : tv::serve::Executor {
+    struct Region {
+        size_t lo, hi;
+        int64_t owner;  // wave sequence for workspace and inputs, -1 - ticket offset for grids
+    };
+    std::mutex m;
+    std::vector<Region> live;
+    std::atomic<int> overlaps{0}, launched{0};
+    std::atomic<uint64_t> gate{~0ull};
+
+    static size_t up(size_t b) { return tv::sched::round_up(b ? b : 1); }
+    size_t workspace_bytes(const std::vector<const Req *> &rs) override {
+        size_t b = 4096;
+        for (const Req *q : rs) b += 8 * (size_t)q->r.nt;
+        return b;
+    }
+    void take(size_t lo, size_t bytes, int64_t owner) {
+        const size_t hi = lo + up(bytes);
+        for (const Region &r : live)
+            if (lo < r.hi && r.lo < hi) overlaps++;
+        live.push_back({lo, hi, owner});
+    }
+    void drop_owner(int64_t owner) {
+        std::vector<Region> keep;
+        for (const Region &r : live)
+            if (r.owner != owner) keep.push_back(r);
+        live.swap(keep);
+    }
+    // the client gives a grid back before releasing its request
+    void drop_grid(size_t off) {
+        std::lock_guard<std::mutex> lk(m);
+        std::vector<Region> keep;
+        for (const Region &r : live)
+            if (!(r.owner < 0 && r.lo == off)) keep.push_back(r);
+        live.swap(keep);
+    }
+    tv_status launch(const Wave &w, const std::vector<const Req *> &rs) override {
+        std::lock_guard<std::mutex> lk(m);
+        take(w.ws_off, workspace_bytes(rs), (int64_t)w.seq);
+        for (const Req *q : rs) {
+            if (q->has_in) take(q->in_off, q->in_bytes, (int64_t)w.seq);
+            take(q->grid_off, q->grid_words * 4, -1);
+        }
+        launched++;
+        return TV_OK;
+    }
+    bool done(const Wave &w) override { return w.seq < gate.load(); }
+    void finish(const Wave &w, std::vector<tv_status> &out) override {
+        std::lock_guard<std::mutex> lk(m);
+        drop_owner((int64_t)w.seq);
+        out.assign(w.tickets.size(), TV_OK);
+    }
+};
+
 // finish() above does not see the requests; the data status of nt == 7 is
 // checked through this executor, which remembers each wave's tets.
 struct StatusExec final : tv::serve::Executor {
@@ -475,8 +534,76 @@ static void stress() {
     printf("ok stress (%lld waves, peak %lld in flight)\n", (long long)s.waves, (long long)s.inflight_peak);
 }
 
+// Clients in the shape of the serving benchmark (one thread submits at
+// random times, another waits for, reads and releases each request in
+// order) against a small arena on two streams, with waves finishing at
+// random times: no region of a wave in flight or of a held grid is ever
+// handed out twice.
+static void regions_disjoint() {
+    Config cfg;
+    cfg.device_bytes = 768 * 1024;
+    cfg.pinned_bytes = 0;
+    cfg.streams = 2;
+    cfg.max_wave_meshes = 16;
+    RegionExec ex;
+    Core core(cfg, &ex);
+    core.start();
+    std::atomic<bool> run{true};
+    std::thread ticker([&] {
+        std::mt19937 rng(9);
+        uint64_t g = 0;
+        while (run.load()) {
+            g += 1 + rng() % 2;
+            ex.gate = g;
+            std::this_thread::sleep_for(std::chrono::microseconds(20 + rng() % 150));
+        }
+        ex.gate = ~0ull;
+    });
+    static float verts[3 * 2000];
+    const int n = 4000;
+    std::vector<std::atomic<int64_t>> tickets(n);
+    for (auto &t : tickets) t = 0;
+    std::atomic<int> ok{0};
+    std::thread collector([&] {
+        for (int i = 0; i < n; ++i) {
+            while (tickets[i].load() == 0) std::this_thread::sleep_for(std::chrono::microseconds(20));
+            const int64_t t = tickets[i].load();
+            if (t < 0) continue;
+            CHECK(core.wait(t, 60.0) == TV_OK);
+            size_t off = 0, words = 0;
+            tv_status ds = -99;
+            CHECK(core.result(t, &off, &words, &ds, nullptr) == TV_OK && ds == TV_OK);
+            ex.drop_grid(off);
+            CHECK(core.release(t) == TV_OK);
+            ok++;
+        }
+    });
+    std::mt19937 rng(77);
+    for (int i = 0; i < n; ++i) {
+        const int64_t nv = 14 + rng() % 1986, nt = 1 + rng() % 4000;
+        const uint32_t in = (rng() % 2) ? TV_REQ_PINNED_INPUTS : TV_REQ_DEVICE_INPUTS;
+        const size_t words = 256u << (rng() % 6);
+        int64_t t = 0;
+        if (core.submit(make_req(verts, nv, nt, in), words, 4096 + 8 * (size_t)nt, &t) != TV_OK) t = -1;
+        tickets[i] = t;
+        if (rng() % 4 == 0) std::this_thread::sleep_for(std::chrono::microseconds(rng() % 100));
+    }
+    collector.join();
+    run = false;
+    ticker.join();
+    tv_server_stats s = core.stats();
+    core.stop();
+    if (ex.overlaps.load())
+        fprintf(stderr, "regions_disjoint: %d overlaps over %d waves\n", ex.overlaps.load(), ex.launched.load());
+    CHECK(ex.overlaps.load() == 0);
+    CHECK(ok.load() == n && s.completed == n && s.device_in_use == 0);
+    printf("ok regions_disjoint (%lld waves, peak %lld in flight)\n", (long long)s.waves,
+           (long long)s.inflight_peak);
+}
+
 int main() {
     setvbuf(stdout, nullptr, _IONBF, 0);
+    regions_disjoint();
     basic_and_overlap();
     front_partly_fits_inputs();
     front_partly_fits_workspace();
