@@ -228,15 +228,17 @@ tv_status tv_batch_run(const tv_batch_plan *plan, void *ws, size_t ws_bytes, voi
  *   min_tiles       tiles are halved (down to 8 x 8 columns) while a grid
  *                   has fewer than this, in [1, 2^20]
  *   chunk_pieces    (tet, tile) pieces per work-queue task, in [64, 65536];
- *                   0 picks about nt / 2048 (a power of two in [256, 16384];
- *                   at least 4096 when the call has 4096 tiles or more)
+ *                   0 picks, for one mesh, about nt / 2048 (a power of two
+ *                   in [256, 16384]; at least 4096 when the call has 4096
+ *                   tiles or more), for a batch about nt / 1024 (a power of
+ *                   two in [256, 65536])
  *   strip_columns   kept columns per lane task, in [1, 64]
  *   piece_cap       tets meeting more tiles take the per-tet large path, [1, 8]
  *   wgs_per_cu      persistent tile workgroups per compute unit, in [1, 8]
  *   cull_columns    a piece whose clipped box has at most this many columns
  *                   skips the per-row culling by its xy hull, in [0, 1024]
  * Defaults (tv_default_params): single {5, 512, 0, 6, 8, 2, 3}, batch
- * {5, 1, 4096, 6, 8, 2, 6}.  tv_set_params validates all fields
+ * {5, 1, 0, 6, 8, 2, 6}.  tv_set_params validates all fields
  * (TV_ERR_INVALID_ARG, nothing changed) and with p == NULL restores the
  * defaults.  The settings are process-wide; each call copies them when it
  * starts, so set them before enqueueing work.  Workspace sizes depend on

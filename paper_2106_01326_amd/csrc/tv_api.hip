@@ -171,7 +171,7 @@ tv::MeshTable make_table(const tv::CallSizes &c, uint8_t *ws, const tv::MeshDesc
     tv::MeshTable T;
     memset(&T, 0, sizeof T);
     T.n = (int32_t)c.meshes;
-    T.chunk = P.chunk ? P.chunk : tv::auto_chunk(c.nt, c.ntiles);
+    T.chunk = P.chunk ? P.chunk : tv::auto_chunk(c.nt, c.ntiles, c.table);
     T.strip = P.strip;
     T.piece_cap = P.piece_cap;
     T.nocull = P.cull;

@@ -30,15 +30,22 @@ struct Params {
 // sizes the queue tasks from the tet count (auto_chunk).  Values from the
 // autotuner's searches on the large, medium and batch workloads.
 constexpr Params kDefaultSingle = {5, 512, 0, 6, 8, 2, 3};
-constexpr Params kDefaultBatch = {5, 1, 4096, 6, 8, 2, 6};
+constexpr Params kDefaultBatch = {5, 1, 0, 6, 8, 2, 6};
 
-// Pieces per work-queue task when Params::chunk is 0: about 4096 tasks in
-// all (pieces, about 2 per tet, / 4096 = nt / 2048), a power of two in
-// [256, 16384].  A call that already has 4096 tiles or more keeps at least
-// 4096 pieces per task: more tasks would only split its tiles into shares
-// that are flushed with atomics.
-inline int32_t auto_chunk(int64_t nt, int64_t ntiles) {
+// Pieces per work-queue task when Params::chunk is 0.  A single mesh: about
+// 4096 tasks in all (pieces, about 2 per tet, / 4096 = nt / 2048), a power
+// of two in [256, 16384]; a call that already has 4096 tiles or more keeps
+// at least 4096 pieces per task: more tasks would only split its tiles into
+// shares that are flushed with atomics.  A batch of meshes: about 1024 tasks
+// (nt / 1024, a power of two in [256, 65536]): its many small tiles then
+// mostly take one task each, written with plain stores, while a small batch
+// (a serving wave of a few meshes) still spreads over the chip.
+inline int32_t auto_chunk(int64_t nt, int64_t ntiles, bool batch) {
     int32_t c = 256;
+    if (batch) {
+        while (c < 65536 && (int64_t)c * 2 * 1024 <= nt) c *= 2;
+        return c;
+    }
     while (c < 16384 && (int64_t)c * 2 * 2048 <= nt) c *= 2;
     if (ntiles >= 4096 && c < 4096) c = 4096;
     return c;
